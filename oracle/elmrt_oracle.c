@@ -1,0 +1,864 @@
+/*
+ * elmrt_oracle.c -- plain FP64 CPU oracle of one time step of the entropic
+ * multi-relaxation-time two-phase lattice Boltzmann model of Hosseini,
+ * Dorschner & Karlin (arXiv:2201.12404).
+ *
+ * TEST INFRASTRUCTURE ONLY: it is loaded by the tests, by the smoke check
+ * and by the CPU-baseline leg of the benchmark, never by the product path.
+ * It shares no code with the HIP library.
+ *
+ * Every quantity is computed the way the paper defines it, in the paper's
+ * order, with no fusion or blocking:
+ *   - moments rho, rho u                         (Sec. 2.2, moment definitions)
+ *   - f^eq and f* in product form                (Sec. 2.1 triplet Psi, Sec. 2.2)
+ *   - force from the psi and rho stencils        (Sec. 2.3, force equation)
+ *   - Phi correction from a central difference   (Sec. 2.2, correction term)
+ *   - k + s + h split by projection on the modified central Hermite basis
+ *                                                (Sec. 2.4, Appendix A)
+ *   - gamma from the entropic scalar products     (Sec. 2.4)
+ *   - mirror state and the LBGK update, then push streaming (Sec. 2, eq. LBGK)
+ *   - Peng-Robinson pressure and the Maxwell equal-area rule by brute force
+ *                                                (Sec. 3.1.1)
+ *
+ * Readings taken where the paper is silent, ambiguous or inconsistent:
+ *   R1  zeta* uses (u + F/rho)^2, i.e. f* is the exact-difference equilibrium
+ *       at the shifted velocity; this is the reading that reproduces the
+ *       closed-form a* vectors of Appendix A (the printed zeta* uses u^2).
+ *   R2  the capillary stencil is used with rho(r+2c) - 2 rho(r+c), so that it
+ *       approximates +rho grad lap rho as in the continuum model (Sec. 2);
+ *       the printed bracket has the opposite sign.
+ *   R3  the sign in front of the psi term is + where P <= P0, - where P > P0,
+ *       so that the term equals -grad(P - P0).
+ *   R4  Phi uses the bare velocity u = sum c f / rho.
+ *   R5  the derivative in Phi is a second-order central difference.
+ *   R6  the trace of the second-order moments belongs to h (bulk viscosity under
+ *       entropic control, Sec. 3.1.2 and Appendix A); s holds the deviatoric
+ *       and off-diagonal second-order moments.
+ *   R7  the D3Q27 moment list repeats a_{x2y2} and omits a_{xyz}; the full
+ *       tensor basis (with a_{xyz}) is used, as in the a* vector.
+ *   R8  central Hermite polynomials per axis: 1, xi, xi^2 - cs^2.
+ *   R10 gamma falls back to 2/omega (h relaxed to equilibrium) when some f*_i
+ *       <= 0 or <dh|dh> <= eps^2 rho, eps = 2^-53.
+ *   R14 nu is interpolated linearly in rho between nu_v at rho_v and nu_l at
+ *       rho_l, clamped outside.
+ *   R15 walls: half-way bounce-back for the populations; for the stencils the
+ *       density is mirrored about the wall plane (rho(-1) = rho(0),
+ *       rho(-2) = rho(1)) and the wall-normal Phi flux is odd.
+ *
+ * Pins (tests that fix this file against something other than itself):
+ *   weights and isotropy, equilibrium moments (rho, 0, ..., 0), extended
+ *   equilibrium moments against the closed-form a* vectors of Appendix A,
+ *   k + s + h = f and s against an explicit Q x Q inverse, gamma = 2 reducing
+ *   to BGK, the rearranged post-collision closed form, stencil orders on
+ *   polynomial fields, exact-in-roundoff mass and momentum conservation,
+ *   invariance of uniform states, mirror symmetry, brute-force Maxwell against
+ *   the closed-form chemical-potential condition, flat-interface coexistence,
+ *   Laplace-law pressure jumps and the bulk value 2/(omega gamma) = 1.
+ */
+#include "elmrt_oracle.h"
+
+#include <float.h>
+#include <math.h>
+#include <stdlib.h>
+#include <string.h>
+#ifdef _OPENMP
+#include <omp.h>
+#endif
+
+/* cs^2 = dr^2 / (3 dt^2) with dr = dt = 1 (Sec. 2.2). */
+static const double CS2 = 1.0 / 3.0;
+
+/* ------------------------------------------------------------------ lattice */
+
+int ora_Q(int D) { return D == 2 ? 9 : 27; }
+
+void ora_velocity(int D, int i, int c[3])
+{
+    c[0] = i % 3 - 1;
+    c[1] = (i / 3) % 3 - 1;
+    c[2] = (D == 3) ? i / 9 - 1 : 0;
+}
+
+static int opposite(int D, int i)
+{
+    int c[3];
+    ora_velocity(D, i, c);
+    int j = (-c[0] + 1) + 3 * (-c[1] + 1);
+    if (D == 3) j += 9 * (-c[2] + 1);
+    return j;
+}
+
+/* Triplet of Sec. 2.1: Psi_0 = 1 - zeta, Psi_{+1} = (xi + zeta)/2, Psi_{-1} = (-xi + zeta)/2. */
+static double triplet(int c, double xi, double zeta)
+{
+    if (c == 0) return 1.0 - zeta;
+    if (c == 1) return 0.5 * (xi + zeta);
+    return 0.5 * (-xi + zeta);
+}
+
+void ora_product_form(int D, double rho, const double* xi, const double* zeta, double* out)
+{
+    int Q = ora_Q(D);
+    for (int i = 0; i < Q; ++i) {
+        int c[3];
+        ora_velocity(D, i, c);
+        double v = rho;
+        for (int a = 0; a < D; ++a) v *= triplet(c[a], xi[a], zeta[a]);
+        out[i] = v;
+    }
+}
+
+/* Weights: product form at xi = 0, zeta = cs^2 (Sec. 2.3). */
+void ora_weights(int D, double* w)
+{
+    double xi[3] = {0, 0, 0}, zeta[3] = {CS2, CS2, CS2};
+    ora_product_form(D, 1.0, xi, zeta, w);
+}
+
+/* Equilibrium: xi = u, zeta = P0/rho + u^2 with P0/rho = cs^2 (Sec. 2.2-2.3). */
+void ora_equilibrium(int D, double rho, const double* u, double* feq)
+{
+    double xi[3] = {0, 0, 0}, zeta[3] = {0, 0, 0};
+    double p0_over_rho = CS2;
+    for (int a = 0; a < D; ++a) {
+        xi[a] = u[a];
+        zeta[a] = p0_over_rho + u[a] * u[a];
+    }
+    ora_product_form(D, rho, xi, zeta, feq);
+}
+
+/* Extended equilibrium: xi* = u + F dt/rho, zeta* = P0/rho + xi*^2 + Phi/rho (reading R1). */
+void ora_extended_equilibrium(int D, double rho, const double* u, const double* F,
+                              const double* Phi, double* fstar)
+{
+    double xi[3] = {0, 0, 0}, zeta[3] = {0, 0, 0};
+    double p0_over_rho = CS2;
+    for (int a = 0; a < D; ++a) {
+        xi[a] = u[a] + F[a] / rho;
+        zeta[a] = p0_over_rho + xi[a] * xi[a] + Phi[a] / rho;
+    }
+    ora_product_form(D, rho, xi, zeta, fstar);
+}
+
+/* ------------------------------------------------- modified Hermite basis */
+
+/* Dense Gauss-Jordan inverse with partial pivoting; returns 0 when singular. */
+static int invert(int n, const double* A, double* Ainv)
+{
+    double M[27 * 54];
+    for (int r = 0; r < n; ++r)
+        for (int c = 0; c < 2 * n; ++c)
+            M[r * 2 * n + c] = (c < n) ? A[r * n + c] : (c - n == r ? 1.0 : 0.0);
+    for (int col = 0; col < n; ++col) {
+        int piv = col;
+        for (int r = col + 1; r < n; ++r)
+            if (fabs(M[r * 2 * n + col]) > fabs(M[piv * 2 * n + col])) piv = r;
+        if (M[piv * 2 * n + col] == 0.0) return 0;
+        if (piv != col)
+            for (int c = 0; c < 2 * n; ++c) {
+                double t = M[col * 2 * n + c];
+                M[col * 2 * n + c] = M[piv * 2 * n + c];
+                M[piv * 2 * n + c] = t;
+            }
+        double d = M[col * 2 * n + col];
+        for (int c = 0; c < 2 * n; ++c) M[col * 2 * n + c] /= d;
+        for (int r = 0; r < n; ++r) {
+            if (r == col) continue;
+            double fac = M[r * 2 * n + col];
+            if (fac == 0.0) continue;
+            for (int c = 0; c < 2 * n; ++c) M[r * 2 * n + c] -= fac * M[col * 2 * n + c];
+        }
+    }
+    for (int r = 0; r < n; ++r)
+        for (int c = 0; c < n; ++c) Ainv[r * n + c] = M[r * 2 * n + n + c];
+    return 1;
+}
+
+/* Central Hermite polynomial of order m in one variable (reading R8). */
+static double hermite1(int m, double xi)
+{
+    if (m == 0) return 1.0;
+    if (m == 1) return xi;
+    return xi * xi - CS2;
+}
+
+/* Tensor multi-index t = m_x + 3 m_y + 9 m_z.  The modified basis replaces the
+ * diagonal second-order tensor moments by differences and the trace
+ * (Appendix A):
+ *   D2Q9 : row t=2 -> a_xx - a_yy,           row t=6 -> a_xx + a_yy
+ *   D3Q27: row t=2 -> a_xx - a_yy, t=6 -> a_xx - a_zz, t=18 -> a_xx + a_yy + a_zz
+ * All other rows are the tensor-product central Hermite moments. */
+static void modified_basis_matrix(int D, double* T /* Q x Q: T[k*Q + t] */)
+{
+    int Q = ora_Q(D);
+    memset(T, 0, sizeof(double) * Q * Q);
+    for (int k = 0; k < Q; ++k) T[k * Q + k] = 1.0;
+    if (D == 2) {
+        T[2 * Q + 2] = 1.0; T[2 * Q + 6] = -1.0;
+        T[6 * Q + 6] = 1.0; T[6 * Q + 2] = 1.0;
+    } else {
+        T[2 * Q + 2] = 1.0;  T[2 * Q + 6] = -1.0;
+        T[6 * Q + 6] = 0.0;  T[6 * Q + 2] = 1.0;  T[6 * Q + 18] = -1.0;
+        T[18 * Q + 18] = 1.0; T[18 * Q + 2] = 1.0; T[18 * Q + 6] = 1.0;
+    }
+}
+
+static void multi_index(int D, int t, int m[3])
+{
+    m[0] = t % 3;
+    m[1] = (t / 3) % 3;
+    m[2] = (D == 3) ? t / 9 : 0;
+}
+
+int ora_moment_class(int D, int k)
+{
+    int m[3];
+    multi_index(D, k, m);
+    int order = m[0] + m[1] + m[2];
+    if (order <= 1) return 0;                       /* a_0, a_x, a_y, a_z */
+    int diag = (D == 2) ? (k == 2 || k == 6) : (k == 2 || k == 6 || k == 18);
+    if (order == 2 && !diag) return 1;              /* a_xy, a_xz, a_yz */
+    if (diag) {
+        int trace = (D == 2) ? (k == 6) : (k == 18);
+        return trace ? 2 : 1;                       /* trace -> h (R6); differences -> s */
+    }
+    return 3;                                       /* third order and above -> h */
+}
+
+/* Modified central Hermite moments a_k = sum_t T[k][t] sum_i H_t(c_i - u) f_i. */
+void ora_moments(int D, const double* u, const double* f, double* a)
+{
+    int Q = ora_Q(D);
+    double T[27 * 27];
+    modified_basis_matrix(D, T);
+    double b[27];
+    for (int t = 0; t < Q; ++t) {
+        int m[3];
+        multi_index(D, t, m);
+        double acc = 0.0;
+        for (int i = 0; i < Q; ++i) {
+            int c[3];
+            ora_velocity(D, i, c);
+            double H = 1.0;
+            for (int al = 0; al < D; ++al) H *= hermite1(m[al], c[al] - u[al]);
+            acc += H * f[i];
+        }
+        b[t] = acc;
+    }
+    for (int k = 0; k < Q; ++k) {
+        double acc = 0.0;
+        for (int t = 0; t < Q; ++t) acc += T[k * Q + t] * b[t];
+        a[k] = acc;
+    }
+}
+
+/* Dual functions of the modified basis at velocity u: Dual[k*Q + i] such that
+ * f_i = sum_k a_k Dual[k][i].  The tensor-product duals are built from the
+ * numerical inverse of the 3 x 3 one-dimensional Hermite matrix per axis, then
+ * combined with the inverse of the basis modification. */
+static void dual_basis(int D, const double* u, double* Dual)
+{
+    int Q = ora_Q(D);
+    double A1inv[3][9];
+    for (int al = 0; al < D; ++al) {
+        double A1[9];
+        for (int m = 0; m < 3; ++m)
+            for (int ci = 0; ci < 3; ++ci) A1[m * 3 + ci] = hermite1(m, (ci - 1) - u[al]);
+        invert(3, A1, A1inv[al]);   /* A1inv[ci*3 + m] */
+    }
+    double Dt[27 * 27];             /* tensor duals: Dt[t*Q + i] */
+    for (int t = 0; t < Q; ++t) {
+        int m[3];
+        multi_index(D, t, m);
+        for (int i = 0; i < Q; ++i) {
+            int c[3];
+            ora_velocity(D, i, c);
+            double v = 1.0;
+            for (int al = 0; al < D; ++al) v *= A1inv[al][(c[al] + 1) * 3 + m[al]];
+            Dt[t * Q + i] = v;
+        }
+    }
+    double T[27 * 27], Tinv[27 * 27];
+    modified_basis_matrix(D, T);
+    invert(Q, T, Tinv);             /* b = Tinv a */
+    for (int k = 0; k < Q; ++k)
+        for (int i = 0; i < Q; ++i) {
+            double acc = 0.0;
+            for (int t = 0; t < Q; ++t) acc += Dt[t * Q + i] * Tinv[t * Q + k];
+            Dual[k * Q + i] = acc;
+        }
+}
+
+/* k + s + h split (Sec. 2.4): projections of f on the conserved, stress and
+ * remaining (trace + higher) moments of the modified basis about u. */
+void ora_split(int D, const double* u, const double* f, double* k, double* s, double* h)
+{
+    int Q = ora_Q(D);
+    double a[27], Dual[27 * 27];
+    ora_moments(D, u, f, a);
+    dual_basis(D, u, Dual);
+    for (int i = 0; i < Q; ++i) {
+        double kk = 0.0, ss = 0.0, hh = 0.0;
+        for (int m = 0; m < Q; ++m) {
+            double v = a[m] * Dual[m * Q + i];
+            int cls = ora_moment_class(D, m);
+            if (cls == 0) kk += v;
+            else if (cls == 1) ss += v;
+            else hh += v;
+        }
+        k[i] = kk;
+        s[i] = ss;
+        h[i] = hh;
+    }
+}
+
+/* --------------------------------------------------------------- collision */
+
+void ora_collide(int D, int collision, double omega, const double* f, const double* F,
+                 const double* Phi, double* fpost, double* gamma_out, int* fallback_out)
+{
+    int Q = ora_Q(D);
+    double rho = 0.0, j[3] = {0, 0, 0}, u[3] = {0, 0, 0};
+    for (int i = 0; i < Q; ++i) {
+        int c[3];
+        ora_velocity(D, i, c);
+        rho += f[i];
+        for (int a = 0; a < D; ++a) j[a] += c[a] * f[i];
+    }
+    for (int a = 0; a < D; ++a) u[a] = j[a] / rho;
+
+    double feq[27], fstar[27];
+    ora_equilibrium(D, rho, u, feq);
+    ora_extended_equilibrium(D, rho, u, F, Phi, fstar);
+
+    double k[27], s[27], h[27], keq[27], seq[27], heq[27];
+    ora_split(D, u, f, k, s, h);
+    ora_split(D, u, feq, keq, seq, heq);
+
+    double gamma = 2.0;
+    int fallback = 0;
+    if (collision == 0) {
+        /* Entropic estimate (Sec. 2.4): gamma/2 = 1/omega - (1 - 1/omega) <ds|dh>/<dh|dh>,
+         * with the scalar product weighted by 1/f*_i. */
+        int nonpos = 0;
+        double sh = 0.0, hh = 0.0;
+        for (int i = 0; i < Q; ++i) {
+            double ds = seq[i] - s[i], dh = heq[i] - h[i];
+            if (!(fstar[i] > 0.0)) nonpos = 1;
+            sh += ds * dh / fstar[i];
+            hh += dh * dh / fstar[i];
+        }
+        double eps = DBL_EPSILON * 0.5;
+        if (nonpos || !(hh > eps * eps * rho)) {
+            gamma = 2.0 / omega;    /* reading R10 */
+            fallback = 1;
+        } else {
+            gamma = 2.0 * (1.0 / omega - (1.0 - 1.0 / omega) * sh / hh);
+        }
+    }
+    for (int i = 0; i < Q; ++i) {
+        double fmirr = k[i] + (2.0 * seq[i] - s[i]) + (1.0 - gamma) * h[i] + gamma * heq[i];
+        fpost[i] = (1.0 - 0.5 * omega) * f[i] + 0.5 * omega * fmirr + (fstar[i] - feq[i]);
+    }
+    if (gamma_out) *gamma_out = gamma;
+    if (fallback_out) *fallback_out = fallback;
+}
+
+/* ----------------------------------------------------------- thermodynamics */
+
+/* Tc from a = 0.45724 R^2 Tc^2/Pc and b = 0.0778 R Tc/Pc (Sec. 3.1). */
+double ora_Tc(double a, double b, double R) { return 0.0778 * a / (0.45724 * b * R); }
+
+double ora_alpha(double acentric, double Tr)
+{
+    double m = 0.37464 + 1.54226 * acentric - 0.26992 * acentric * acentric;
+    double t = 1.0 + m * (1.0 - sqrt(Tr));
+    return t * t;
+}
+
+static double pr_pressure(double a_alpha, double b, double RT, double rho)
+{
+    return rho * RT / (1.0 - b * rho) - a_alpha * rho * rho / (1.0 + 2.0 * rho * b - b * b * rho * rho);
+}
+
+static double pr_dpressure(double a_alpha, double b, double RT, double rho)
+{
+    double g = 1.0 + 2.0 * b * rho - b * b * rho * rho;
+    double dg = 2.0 * b - 2.0 * b * b * rho;
+    double one_m = 1.0 - b * rho;
+    return RT / (one_m * one_m) - a_alpha * (2.0 * rho * g - rho * rho * dg) / (g * g);
+}
+
+double ora_pressure(const ora_params* p, double rho)
+{
+    double Tc = ora_Tc(p->a, p->b, p->R);
+    double T = p->Tr * Tc;
+    return pr_pressure(p->a * ora_alpha(p->acentric, p->Tr), p->b, p->R * T, rho);
+}
+
+typedef struct { double aal, b, RT, psat; } maxwell_ctx;
+
+static double maxwell_integrand(const maxwell_ctx* m, double rho)
+{
+    return (m->psat - pr_pressure(m->aal, m->b, m->RT, rho)) / (rho * rho);
+}
+
+/* Composite Simpson rule in x = ln(rho): int g(rho) d rho = int g(e^x) e^x dx.
+ * The integrand is analytic on [rho_v, rho_l] (away from 1/b), so a fixed fine
+ * panel count gives close to double precision. */
+static double simpson(const maxwell_ctx* m, double a, double b)
+{
+    const int NP = 20000;   /* even */
+    double xa = log(a), xb = log(b);
+    double h = (xb - xa) / NP;
+    double acc = 0.0;
+    for (int k = 0; k <= NP; ++k) {
+        double x = xa + h * k;
+        double r = exp(x);
+        double g = maxwell_integrand(m, r) * r;
+        double wgt = (k == 0 || k == NP) ? 1.0 : ((k & 1) ? 4.0 : 2.0);
+        acc += wgt * g;
+    }
+    return acc * h / 3.0;
+}
+
+/* root of P(rho) = target in [lo, hi], P monotone increasing there */
+static double bisect_pressure(const maxwell_ctx* m, double target, double lo, double hi)
+{
+    for (int it = 0; it < 400; ++it) {
+        double mid = 0.5 * (lo + hi);
+        if (mid == lo || mid == hi) break;
+        if (pr_pressure(m->aal, m->b, m->RT, mid) < target) lo = mid;
+        else hi = mid;
+    }
+    return 0.5 * (lo + hi);
+}
+
+/* Maxwell equal-area rule (Sec. 3.1.1) by brute force: bisection on P_sat, with
+ * the two outer roots of P = P_sat found by bisection and the area integral
+ * evaluated by composite Simpson quadrature. */
+int ora_maxwell(double a, double b, double R, double acentric, double Tr,
+                double* rho_v, double* rho_l, double* p_sat)
+{
+    if (!(Tr > 0.0 && Tr < 1.0) || !(a > 0.0) || !(b > 0.0) || !(R > 0.0)) return -1;
+    maxwell_ctx m;
+    double Tc = ora_Tc(a, b, R);
+    m.aal = a * ora_alpha(acentric, Tr);
+    m.b = b;
+    m.RT = R * Tr * Tc;
+    /* spinodals: sign changes of dP/drho on a fine scan of (0, 1/b) */
+    const int NS = 200000;
+    double rmax = 1.0 / b;
+    double s1 = -1.0, s2 = -1.0;
+    double prev = pr_dpressure(m.aal, b, m.RT, rmax * 1e-9);
+    double prev_r = rmax * 1e-9;
+    for (int k = 1; k < NS; ++k) {
+        double r = rmax * k / NS;
+        double d = pr_dpressure(m.aal, b, m.RT, r);
+        if (s1 < 0.0 && prev > 0.0 && d <= 0.0) {
+            double lo = prev_r, hi = r;
+            for (int it = 0; it < 200; ++it) {
+                double mid = 0.5 * (lo + hi);
+                if (pr_dpressure(m.aal, b, m.RT, mid) > 0.0) lo = mid; else hi = mid;
+            }
+            s1 = 0.5 * (lo + hi);
+        } else if (s1 > 0.0 && s2 < 0.0 && prev < 0.0 && d >= 0.0) {
+            double lo = prev_r, hi = r;
+            for (int it = 0; it < 200; ++it) {
+                double mid = 0.5 * (lo + hi);
+                if (pr_dpressure(m.aal, b, m.RT, mid) < 0.0) lo = mid; else hi = mid;
+            }
+            s2 = 0.5 * (lo + hi);
+            break;
+        }
+        prev = d;
+        prev_r = r;
+    }
+    if (s1 < 0.0 || s2 < 0.0) return -2;
+    double pmax = pr_pressure(m.aal, b, m.RT, s1);
+    double pmin = pr_pressure(m.aal, b, m.RT, s2);
+    double lo = pmin > 0.0 ? pmin : 0.0, hi = pmax;
+    double rv = 0.0, rl = 0.0;
+    for (int it = 0; it < 200; ++it) {
+        double ps = 0.5 * (lo + hi);
+        if (ps == lo || ps == hi) break;
+        m.psat = ps;
+        rv = bisect_pressure(&m, ps, 0.0, s1);
+        rl = bisect_pressure(&m, ps, s2, rmax * (1.0 - 1e-15));
+        double I = simpson(&m, rv, s1) + simpson(&m, s1, s2) + simpson(&m, s2, rl);
+        if (I > 0.0) hi = ps; else lo = ps;
+    }
+    m.psat = 0.5 * (lo + hi);
+    *p_sat = m.psat;
+    *rho_v = bisect_pressure(&m, m.psat, 0.0, s1);
+    *rho_l = bisect_pressure(&m, m.psat, s2, rmax * (1.0 - 1e-15));
+    return 0;
+}
+
+/* omega = dt / (rho nu / P0 + dt/2) with P0 = rho cs^2 (Sec. 2), nu(rho) by R14. */
+double ora_omega(const ora_params* p, double rho)
+{
+    double nu = p->nu_l;
+    if (p->rho_l > p->rho_v) {
+        double x = (rho - p->rho_v) / (p->rho_l - p->rho_v);
+        if (x < 0.0) x = 0.0;
+        if (x > 1.0) x = 1.0;
+        nu = p->nu_v + (p->nu_l - p->nu_v) * x;
+    }
+    double P0 = rho * CS2;
+    return 1.0 / (rho * nu / P0 + 0.5);
+}
+
+/* ----------------------------------------------------------------- grid ops */
+
+typedef struct {
+    const ora_params* p;
+    int Q;
+    const double* f;    /* populations, always present */
+    const double* rho;  /* optional precomputed density */
+    const double* q;    /* optional precomputed flux q[a*N + cell] */
+} grid_ctx;
+
+static int64_t ncells(const ora_params* p) { return (int64_t)p->n[0] * p->n[1] * p->n[2]; }
+
+/* Map a coordinate onto the grid: periodic wrap, or mirror about the wall plane
+ * at -1/2 (and n - 1/2).  *mirrored is set when a wall mirror was applied. */
+static int map_coord(int x, int n, int bc, int* mirrored)
+{
+    if (bc == 0) {
+        x %= n;
+        if (x < 0) x += n;
+        return x;
+    }
+    while (x < 0 || x >= n) {
+        if (x < 0) x = -1 - x;
+        else x = 2 * n - 1 - x;
+        *mirrored ^= 1;
+    }
+    return x;
+}
+
+static int64_t cell_index(const ora_params* p, const int x[3])
+{
+    return x[0] + (int64_t)p->n[0] * (x[1] + (int64_t)p->n[1] * x[2]);
+}
+
+static double rho_of_cell(const grid_ctx* C, int64_t idx)
+{
+    if (C->rho) return C->rho[idx];
+    double r = 0.0;
+    for (int i = 0; i < C->Q; ++i) r += C->f[idx * C->Q + i];
+    return r;
+}
+
+/* density at an arbitrary (possibly ghost) position */
+static double rho_at(const grid_ctx* C, const int x[3])
+{
+    int y[3], mir[3] = {0, 0, 0};
+    for (int a = 0; a < 3; ++a) y[a] = map_coord(x[a], C->p->n[a], C->p->bc[a], &mir[a]);
+    return rho_of_cell(C, cell_index(C->p, y));
+}
+
+/* pseudo-potential psi = sqrt(|P - P0|) (Sec. 2.3), P0 = rho cs^2 */
+static double psi_of(const ora_params* p, double rho)
+{
+    double P = ora_pressure(p, rho);
+    double P0 = rho * CS2;
+    return (P > P0) ? sqrt(P - P0) : sqrt(P0 - P);
+}
+
+/* q_a = rho u_a (u_a^2 + 3 P0/rho - 3 cs^2), the flux differentiated in Phi (Sec. 2.2) */
+static double q_of_cell(const grid_ctx* C, int64_t idx, int a)
+{
+    if (C->q) return C->q[(int64_t)a * ncells(C->p) + idx];
+    const double* fc = C->f + idx * C->Q;
+    double rho = 0.0, j = 0.0;
+    for (int i = 0; i < C->Q; ++i) {
+        int c[3];
+        ora_velocity(C->p->D, i, c);
+        rho += fc[i];
+        j += c[a] * fc[i];
+    }
+    double u = j / rho;
+    double P0 = rho * CS2;
+    return rho * u * (u * u + 3.0 * P0 / rho - 3.0 * CS2);
+}
+
+static double q_at(const grid_ctx* C, const int x[3], int a)
+{
+    int y[3], mir[3] = {0, 0, 0};
+    for (int b = 0; b < 3; ++b) y[b] = map_coord(x[b], C->p->n[b], C->p->bc[b], &mir[b]);
+    double v = q_of_cell(C, cell_index(C->p, y), a);
+    return mir[a] ? -v : v;
+}
+
+/* delta_t F at cell x (Sec. 2.3 with readings R2 and R3) */
+static void force_at(const grid_ctx* C, const int x[3], double F[3], int* p_above)
+{
+    const ora_params* p = C->p;
+    int D = p->D, Q = C->Q;
+    double w[27];
+    ora_weights(D, w);
+    double rho = rho_at(C, x);
+    double P = ora_pressure(p, rho);
+    double P0 = rho * CS2;
+    double psi_r = (P > P0) ? sqrt(P - P0) : sqrt(P0 - P);
+    double sign = (P > P0) ? -1.0 : 1.0;
+    double G[3] = {0, 0, 0}, K[3] = {0, 0, 0};
+    for (int i = 0; i < Q; ++i) {
+        int c[3];
+        ora_velocity(D, i, c);
+        int x1[3], x2[3];
+        for (int a = 0; a < 3; ++a) {
+            x1[a] = x[a] + c[a];
+            x2[a] = x[a] + 2 * c[a];
+        }
+        double rho1 = rho_at(C, x1), rho2 = rho_at(C, x2);
+        double psi1 = psi_of(p, rho1), psi2 = psi_of(p, rho2);
+        for (int a = 0; a < D; ++a) {
+            G[a] += w[i] / CS2 * c[a] * (4.0 / 3.0 * psi1 - 1.0 / 6.0 * psi2);
+            K[a] += w[i] / CS2 * c[a] * (rho2 - 2.0 * rho1);
+        }
+    }
+    for (int a = 0; a < 3; ++a) F[a] = 0.0;
+    for (int a = 0; a < D; ++a) F[a] = sign * 2.0 * psi_r * G[a] + p->kappa * rho * K[a];
+    if (p_above) *p_above = (P > P0);
+}
+
+/* post-collision populations at cell x */
+static void post_collision_at(const grid_ctx* C, const int x[3], double* fpost, double* gamma,
+                              int* fallback, int* p_above)
+{
+    const ora_params* p = C->p;
+    int D = p->D;
+    double F[3], Phi[3] = {0, 0, 0};
+    force_at(C, x, F, p_above);
+    int64_t idx = cell_index(p, x);
+    double rho = rho_of_cell(C, idx);
+    double omega = ora_omega(p, rho);
+    for (int a = 0; a < D; ++a) {
+        int xp[3] = {x[0], x[1], x[2]}, xm[3] = {x[0], x[1], x[2]};
+        xp[a] += 1;
+        xm[a] -= 1;
+        /* Phi_aa = (1 - omega/2) dt d_a q_a, central difference (reading R5) */
+        Phi[a] = (1.0 - 0.5 * omega) * 0.5 * (q_at(C, xp, a) - q_at(C, xm, a));
+    }
+    ora_collide(D, p->collision, omega, C->f + idx * C->Q, F, Phi, fpost, gamma, fallback);
+}
+
+static int check_params(const ora_params* p)
+{
+    if (p->D != 2 && p->D != 3) return -1;
+    if (p->D == 2 && p->n[2] != 1) return -1;
+    for (int a = 0; a < p->D; ++a) {
+        if (p->n[a] < 2) return -1;
+        if (p->bc[a] != 0 && p->bc[a] != 1) return -1;
+    }
+    return 0;
+}
+
+int ora_init_equilibrium(const ora_params* p, const double* rho0, const double* u0, double* f)
+{
+    if (check_params(p)) return -1;
+    int Q = ora_Q(p->D);
+    int64_t N = ncells(p);
+    for (int64_t c = 0; c < N; ++c) {
+        double u[3] = {0, 0, 0};
+        for (int a = 0; a < p->D; ++a) u[a] = u0[(int64_t)a * N + c];
+        ora_equilibrium(p->D, rho0[c], u, f + c * Q);
+    }
+    return 0;
+}
+
+static void coords_of(const ora_params* p, int64_t idx, int x[3])
+{
+    x[0] = (int)(idx % p->n[0]);
+    x[1] = (int)((idx / p->n[0]) % p->n[1]);
+    x[2] = (int)(idx / ((int64_t)p->n[0] * p->n[1]));
+}
+
+int ora_force_field(const ora_params* p, const double* rho, double* F)
+{
+    if (check_params(p)) return -1;
+    grid_ctx C = {p, ora_Q(p->D), NULL, rho, NULL};
+    int64_t N = ncells(p);
+#pragma omp parallel for schedule(static)
+    for (int64_t c = 0; c < N; ++c) {
+        int x[3];
+        coords_of(p, c, x);
+        force_at(&C, x, F + c * 3, NULL);
+    }
+    return 0;
+}
+
+int ora_step(const ora_params* p, double* f, int64_t nsteps, ora_stats* st, double* gamma_field)
+{
+    if (check_params(p)) return -1;
+    int D = p->D, Q = ora_Q(D);
+    int64_t N = ncells(p);
+    double* rho = (double*)malloc(sizeof(double) * N);
+    double* q = (double*)malloc(sizeof(double) * N * 3);
+    double* fpost = (double*)malloc(sizeof(double) * N * Q);
+    if (!rho || !q || !fpost) {
+        free(rho); free(q); free(fpost);
+        return -3;
+    }
+    int64_t n_above = 0, n_fb = 0, n_bad = 0;
+    double gmin = INFINITY, gmax = -INFINITY;
+    for (int64_t step = 0; step < nsteps; ++step) {
+        int last = (step == nsteps - 1);
+        /* A: moments and the flux q of every cell */
+        grid_ctx C0 = {p, Q, f, NULL, NULL};
+#pragma omp parallel for schedule(static)
+        for (int64_t c = 0; c < N; ++c) {
+            rho[c] = rho_of_cell(&C0, c);
+            for (int a = 0; a < 3; ++a) q[(int64_t)a * N + c] = (a < D) ? q_of_cell(&C0, c, a) : 0.0;
+        }
+        /* B: force, Phi and collision of every cell */
+        grid_ctx C = {p, Q, f, rho, q};
+        int64_t la = 0, lf = 0, lb = 0;
+        double lmin = INFINITY, lmax = -INFINITY;
+#pragma omp parallel for schedule(static) reduction(+:la,lf,lb) reduction(min:lmin) reduction(max:lmax)
+        for (int64_t c = 0; c < N; ++c) {
+            int x[3];
+            coords_of(p, c, x);
+            double g;
+            int fb, pa;
+            post_collision_at(&C, x, fpost + c * Q, &g, &fb, &pa);
+            if (last) {
+                double om = ora_omega(p, rho[c]);
+                double v = 2.0 / (om * g);
+                la += pa;
+                lf += fb;
+                if (!(rho[c] > 0.0) || !isfinite(rho[c])) lb += 1;
+                if (v < lmin) lmin = v;
+                if (v > lmax) lmax = v;
+                if (gamma_field) gamma_field[c] = g;
+            }
+        }
+        if (last) {
+            n_above = la; n_fb = lf; n_bad = lb; gmin = lmin; gmax = lmax;
+        }
+        /* C: streaming f_i(r + c_i, t + 1) = f'_i(r); half-way bounce-back at walls */
+#pragma omp parallel for schedule(static)
+        for (int64_t c = 0; c < N; ++c) {
+            int x[3];
+            coords_of(p, c, x);
+            for (int i = 0; i < Q; ++i) {
+                int cv[3];
+                ora_velocity(D, i, cv);
+                int t[3], out = 0;
+                for (int a = 0; a < 3; ++a) {
+                    t[a] = x[a] + cv[a];
+                    if (p->bc[a] == 1 && (t[a] < 0 || t[a] >= p->n[a])) out = 1;
+                    else {
+                        t[a] %= p->n[a];
+                        if (t[a] < 0) t[a] += p->n[a];
+                    }
+                }
+                if (out) f[c * Q + opposite(D, i)] = fpost[c * Q + i];
+                else f[cell_index(p, t) * Q + i] = fpost[c * Q + i];
+            }
+        }
+    }
+    if (st) {
+        st->cells_p_above_p0 = n_above;
+        st->cells_gamma_fallback = n_fb;
+        st->min_2_over_omega_gamma = gmin;
+        st->max_2_over_omega_gamma = gmax;
+        st->nonfinite = n_bad;
+    }
+    free(rho);
+    free(q);
+    free(fpost);
+    return 0;
+}
+
+/* Neumaier compensated summation */
+typedef struct { double s, c; } csum;
+static void csum_add(csum* a, double x)
+{
+    double t = a->s + x;
+    if (fabs(a->s) >= fabs(x)) a->c += (a->s - t) + x;
+    else a->c += (x - t) + a->s;
+    a->s = t;
+}
+
+int ora_macros(const ora_params* p, const double* f, double* rho, double* u, double* sums)
+{
+    if (check_params(p)) return -1;
+    int D = p->D, Q = ora_Q(D);
+    int64_t N = ncells(p);
+    csum S[4] = {{0, 0}, {0, 0}, {0, 0}, {0, 0}};
+    for (int64_t c = 0; c < N; ++c) {
+        double r = 0.0, j[3] = {0, 0, 0};
+        for (int i = 0; i < Q; ++i) {
+            int cv[3];
+            ora_velocity(D, i, cv);
+            r += f[c * Q + i];
+            for (int a = 0; a < D; ++a) j[a] += cv[a] * f[c * Q + i];
+        }
+        if (rho) rho[c] = r;
+        for (int a = 0; a < D; ++a)
+            if (u) u[(int64_t)a * N + c] = j[a] / r;
+        csum_add(&S[0], r);
+        for (int a = 0; a < D; ++a) csum_add(&S[1 + a], j[a]);
+    }
+    if (sums)
+        for (int k = 0; k < 4; ++k) sums[k] = S[k].s + S[k].c;
+    return 0;
+}
+
+int ora_update_cells(const ora_params* p, const double* f, int64_t nc, const int64_t* cells,
+                     double* fout)
+{
+    if (check_params(p)) return -1;
+    int D = p->D, Q = ora_Q(D);
+    int64_t N = ncells(p);
+    grid_ctx C = {p, Q, f, NULL, NULL};
+#pragma omp parallel for schedule(dynamic)
+    for (int64_t k = 0; k < nc; ++k) {
+        if (cells[k] < 0 || cells[k] >= N) continue;
+        int x[3];
+        coords_of(p, cells[k], x);
+        double own[27];
+        int have_own = 0;
+        for (int i = 0; i < Q; ++i) {
+            int cv[3];
+            ora_velocity(D, i, cv);
+            int s[3], out = 0;
+            for (int a = 0; a < 3; ++a) {
+                s[a] = x[a] - cv[a];
+                if (p->bc[a] == 1 && (s[a] < 0 || s[a] >= p->n[a])) out = 1;
+                else {
+                    s[a] %= p->n[a];
+                    if (s[a] < 0) s[a] += p->n[a];
+                }
+            }
+            if (out) {
+                /* the population leaving x towards the wall returns reflected */
+                if (!have_own) {
+                    post_collision_at(&C, x, own, NULL, NULL, NULL);
+                    have_own = 1;
+                }
+                fout[k * Q + i] = own[opposite(D, i)];
+            } else {
+                double src[27];
+                post_collision_at(&C, s, src, NULL, NULL, NULL);
+                fout[k * Q + i] = src[i];
+            }
+        }
+    }
+    return 0;
+}
+
+int ora_set_threads(int nthreads)
+{
+#ifdef _OPENMP
+    if (nthreads > 0) omp_set_num_threads(nthreads);
+    return omp_get_max_threads();
+#else
+    (void)nthreads;
+    return 1;
+#endif
+}
