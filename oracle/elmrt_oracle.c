@@ -41,6 +41,9 @@
  *       <= 0 or <dh|dh> <= eps^2 rho, eps = 2^-53.
  *   R14 nu is interpolated linearly in rho between nu_v at rho_v and nu_l at
  *       rho_l, clamped outside.
+ *   R16 the initial state is the equilibrium at the bare velocity that gives
+ *       the prescribed fluid velocity u + F/(2 rho) (ora_init_fluid); starting
+ *       at bare u = 0 instead gives every interface an inward impulse F/2.
  *   R15 walls: half-way bounce-back for the populations; for the stencils the
  *       density is mirrored about the wall plane (rho(-1) = rho(0),
  *       rho(-2) = rho(1)) and the wall-normal Phi flux is odd.
@@ -203,6 +206,18 @@ static void modified_basis_matrix(int D, double* T /* Q x Q: T[k*Q + t] */)
     }
 }
 
+/* The modification matrix and its inverse do not depend on u: built once. */
+static double g_T[2][27 * 27], g_Tinv[2][27 * 27];
+
+__attribute__((constructor)) static void init_basis(void)
+{
+    for (int k = 0; k < 2; ++k) {
+        int D = k + 2;
+        modified_basis_matrix(D, g_T[k]);
+        invert(ora_Q(D), g_T[k], g_Tinv[k]);
+    }
+}
+
 static void multi_index(int D, int t, int m[3])
 {
     m[0] = t % 3;
@@ -229,8 +244,7 @@ int ora_moment_class(int D, int k)
 void ora_moments(int D, const double* u, const double* f, double* a)
 {
     int Q = ora_Q(D);
-    double T[27 * 27];
-    modified_basis_matrix(D, T);
+    const double* T = g_T[D - 2];
     double b[27];
     for (int t = 0; t < Q; ++t) {
         int m[3];
@@ -252,11 +266,11 @@ void ora_moments(int D, const double* u, const double* f, double* a)
     }
 }
 
-/* Dual functions of the modified basis at velocity u: Dual[k*Q + i] such that
- * f_i = sum_k a_k Dual[k][i].  The tensor-product duals are built from the
- * numerical inverse of the 3 x 3 one-dimensional Hermite matrix per axis, then
- * combined with the inverse of the basis modification. */
-static void dual_basis(int D, const double* u, double* Dual)
+/* Tensor-product dual functions at velocity u: Dt[t*Q + i] such that
+ * f_i = sum_t b_t Dt[t][i] for the tensor moments b_t = sum_i H_t(c_i - u) f_i.
+ * Built from the numerical inverse of the 3 x 3 one-dimensional Hermite
+ * matrix of each axis. */
+static void tensor_duals(int D, const double* u, double* Dt)
 {
     int Q = ora_Q(D);
     double A1inv[3][9];
@@ -266,7 +280,6 @@ static void dual_basis(int D, const double* u, double* Dual)
             for (int ci = 0; ci < 3; ++ci) A1[m * 3 + ci] = hermite1(m, (ci - 1) - u[al]);
         invert(3, A1, A1inv[al]);   /* A1inv[ci*3 + m] */
     }
-    double Dt[27 * 27];             /* tensor duals: Dt[t*Q + i] */
     for (int t = 0; t < Q; ++t) {
         int m[3];
         multi_index(D, t, m);
@@ -278,37 +291,37 @@ static void dual_basis(int D, const double* u, double* Dual)
             Dt[t * Q + i] = v;
         }
     }
-    double T[27 * 27], Tinv[27 * 27];
-    modified_basis_matrix(D, T);
-    invert(Q, T, Tinv);             /* b = Tinv a */
-    for (int k = 0; k < Q; ++k)
-        for (int i = 0; i < Q; ++i) {
-            double acc = 0.0;
-            for (int t = 0; t < Q; ++t) acc += Dt[t * Q + i] * Tinv[t * Q + k];
-            Dual[k * Q + i] = acc;
-        }
 }
 
 /* k + s + h split (Sec. 2.4): projections of f on the conserved, stress and
- * remaining (trace + higher) moments of the modified basis about u. */
+ * remaining (trace + higher) moments of the modified basis about u.  Each
+ * part keeps its own moments a_k, goes back to tensor moments with the
+ * inverse of the basis modification, then to populations with the duals. */
 void ora_split(int D, const double* u, const double* f, double* k, double* s, double* h)
 {
     int Q = ora_Q(D);
-    double a[27], Dual[27 * 27];
+    const double* Tinv = g_Tinv[D - 2];
+    double a[27], Dt[27 * 27];
     ora_moments(D, u, f, a);
-    dual_basis(D, u, Dual);
-    for (int i = 0; i < Q; ++i) {
-        double kk = 0.0, ss = 0.0, hh = 0.0;
+    tensor_duals(D, u, Dt);
+    double* out[3] = {k, s, h};
+    for (int cls = 0; cls < 3; ++cls) {
+        double am[27], bm[27];
         for (int m = 0; m < Q; ++m) {
-            double v = a[m] * Dual[m * Q + i];
-            int cls = ora_moment_class(D, m);
-            if (cls == 0) kk += v;
-            else if (cls == 1) ss += v;
-            else hh += v;
+            int c = ora_moment_class(D, m);
+            int part = (c == 0) ? 0 : (c == 1 ? 1 : 2);
+            am[m] = (part == cls) ? a[m] : 0.0;
         }
-        k[i] = kk;
-        s[i] = ss;
-        h[i] = hh;
+        for (int t = 0; t < Q; ++t) {
+            double acc = 0.0;
+            for (int m = 0; m < Q; ++m) acc += Tinv[t * Q + m] * am[m];
+            bm[t] = acc;
+        }
+        for (int i = 0; i < Q; ++i) {
+            double acc = 0.0;
+            for (int t = 0; t < Q; ++t) acc += bm[t] * Dt[t * Q + i];
+            out[cls][i] = acc;
+        }
     }
 }
 
@@ -675,6 +688,28 @@ static void coords_of(const ora_params* p, int64_t idx, int x[3])
     x[0] = (int)(idx % p->n[0]);
     x[1] = (int)((idx / p->n[0]) % p->n[1]);
     x[2] = (int)(idx / ((int64_t)p->n[0] * p->n[1]));
+}
+
+/* Start from a prescribed fluid velocity.  With the exact-difference forcing
+ * the fluid velocity is u + F dt/(2 rho) (reading R16), so the equilibrium is
+ * taken at the bare velocity u0 - F(rho0) dt/(2 rho0), F being the force of
+ * Sec. 2.3 on the initial density. */
+int ora_init_fluid(const ora_params* p, const double* rho0, const double* u0, double* f)
+{
+    if (check_params(p)) return -1;
+    int D = p->D, Q = ora_Q(D);
+    int64_t N = ncells(p);
+    grid_ctx C = {p, Q, NULL, rho0, NULL};
+#pragma omp parallel for schedule(static)
+    for (int64_t c = 0; c < N; ++c) {
+        int x[3];
+        coords_of(p, c, x);
+        double F[3], u[3] = {0, 0, 0};
+        force_at(&C, x, F, NULL);
+        for (int a = 0; a < D; ++a) u[a] = u0[(int64_t)a * N + c] - F[a] / (2.0 * rho0[c]);
+        ora_equilibrium(D, rho0[c], u, f + c * Q);
+    }
+    return 0;
 }
 
 int ora_force_field(const ora_params* p, const double* rho, double* F)

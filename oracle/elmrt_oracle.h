@@ -79,6 +79,8 @@ int    ora_force_field(const ora_params* p, const double* rho, double* F /* [cel
 /* Grid operations. */
 int    ora_init_equilibrium(const ora_params* p, const double* rho0, const double* u0 /* [a*N+cell] */,
                             double* f);
+/* f = f^eq(rho0, u0 - F(rho0)/(2 rho0)): u0 is the fluid velocity. */
+int    ora_init_fluid(const ora_params* p, const double* rho0, const double* u0, double* f);
 int    ora_step(const ora_params* p, double* f, int64_t nsteps, ora_stats* st,
                 double* gamma_field /* NULL or [N], gamma of the last step */);
 int    ora_macros(const ora_params* p, const double* f, double* rho, double* u /* [a*N+cell] */,

@@ -97,6 +97,8 @@ def lib():
         L.ora_force_field.restype = ctypes.c_int
         L.ora_init_equilibrium.argtypes = [ctypes.POINTER(_Params), _dp, _dp, _dp]
         L.ora_init_equilibrium.restype = ctypes.c_int
+        L.ora_init_fluid.argtypes = [ctypes.POINTER(_Params), _dp, _dp, _dp]
+        L.ora_init_fluid.restype = ctypes.c_int
         L.ora_step.argtypes = [ctypes.POINTER(_Params), _dp, ctypes.c_int64,
                                ctypes.POINTER(_Stats), _dp]
         L.ora_step.restype = ctypes.c_int
@@ -281,6 +283,18 @@ def init_equilibrium(p: Params, rho0: np.ndarray, u0: np.ndarray) -> np.ndarray:
     f = np.zeros((p.N, p.Q))
     cp = p.c()
     rc = lib().ora_init_equilibrium(ctypes.byref(cp), _ptr(rho0), _ptr(u0), _ptr(f))
+    if rc != 0:
+        raise ValueError("invalid oracle parameters")
+    return f
+
+
+def init_fluid(p: Params, rho0: np.ndarray, u0: np.ndarray) -> np.ndarray:
+    """f = f^eq at the bare velocity u0 - F(rho0)/(2 rho0): u0 is the fluid velocity."""
+    rho0 = np.ascontiguousarray(rho0, dtype=np.float64).reshape(-1)
+    u0 = np.ascontiguousarray(u0, dtype=np.float64).reshape(p.D, -1)
+    f = np.zeros((p.N, p.Q))
+    cp = p.c()
+    rc = lib().ora_init_fluid(ctypes.byref(cp), _ptr(rho0), _ptr(u0), _ptr(f))
     if rc != 0:
         raise ValueError("invalid oracle parameters")
     return f

@@ -183,3 +183,23 @@ def test_update_cells_matches_full_step():
         part = O.update_cells(p, f, cells)
         O.step(p, f, 1)
         np.testing.assert_allclose(part, f[cells], rtol=0, atol=1e-15 * rl)
+
+
+@pytest.mark.parametrize("D,n,bc", [(2, (20, 18, 1), (0, 0, 0)), (2, (20, 18, 1), (0, 1, 0)),
+                                    (3, (9, 8, 10), (0, 0, 1))])
+def test_fluid_velocity_initialisation(D, n, bc):
+    """With the exact-difference forcing the fluid velocity is u + F/(2 rho);
+    the initial state built from a prescribed fluid velocity u0 has density
+    rho0 and u + F(rho)/(2 rho) = u0 (definition checked from the populations)."""
+    rho0, _, rv, rl = _drop_state(D, n, R=4)
+    u0 = np.random.default_rng(2).uniform(-0.01, 0.01, (D, rho0.size))
+    p = O.Params(D=D, n=n, bc=bc, kappa=0.03, rho_l=rl, rho_v=rv)
+    f = O.init_fluid(p, rho0, u0)
+    rho, u, _ = O.macros(p, f)
+    F = O.force_field(p, rho)
+    np.testing.assert_allclose(rho, rho0, rtol=0, atol=1e-14 * rl)
+    np.testing.assert_allclose(u + F / (2 * rho), u0, rtol=0, atol=1e-14)
+    # and it is the equilibrium there: the non-equilibrium part vanishes
+    c = B.velocities(D).astype(float)
+    for cell in (0, rho0.size // 2, rho0.size - 1):
+        np.testing.assert_allclose(f[cell], O.equilibrium(D, rho[cell], u[:, cell]), atol=1e-15 * rl)
