@@ -1,0 +1,195 @@
+"""Throughput of the fused stream + collide step on one MI355X.
+
+Workload: D3Q27, FP32, 256^3 drop impact on a thin film (x, y periodic, walls
+in z, density ratio 1000), seeded synthetic initial state resident in HBM
+before the timed region.  A step is one moment kernel plus one fused
+stencil/collision kernel over all cells.
+
+Prints one JSON line: MLUPS, ms per step, the roofline of the dominant
+(collision) kernel timed with HIP events on the library's stream, and a CPU
+baseline (the FP64 oracle on the host cores, on a bounded sample).
+"""
+from __future__ import annotations
+
+import argparse
+import hashlib
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+HBM_PEAK_GBS = 8000.0
+
+
+def kernel_source_hash() -> str:
+    h = hashlib.sha256()
+    for fn in ("elmrt_kernels.hip", "elmrt_internal.h"):
+        with open(os.path.join(ROOT, "paper_2201_12404_amd", "csrc", fn), "rb") as f:
+            h.update(f.read())
+    return h.hexdigest()[:16]
+
+
+def algorithmic_bytes(D: int, es: int):
+    """Per lattice update: (moment kernel, collision kernel) bytes.
+    moment   : Q populations read, rho and D flux components written
+    collision: Q populations read and written, rho and D fluxes read"""
+    Q = 9 if D == 2 else 27
+    return (Q * es + (1 + D) * es, 2 * Q * es + (1 + D) * es)
+
+
+def measured_traffic(tag: str):
+    """HBM bytes per collision launch from the committed rocprofv3 counter
+    summary, if it was taken on the current kernel source."""
+    path = os.path.join(ROOT, "profiles", f"traffic_{tag}.json")
+    if not os.path.exists(path):
+        return None
+    with open(path) as f:
+        d = json.load(f)
+    if d.get("kernel_source_sha") != kernel_source_hash():
+        return None
+    return d.get("bytes_per_launch")
+
+
+def cpu_baseline(w, budget_s: float = 20.0):
+    """The FP64 oracle as it stands, timed on a bounded sample of the same
+    workload: a 128 x 128 x 96 block cut from the 256^3 initial state around the
+    drop and the film (own periodic x/y, walls in z), stepped on all host
+    threads."""
+    import numpy as np
+
+    from oracle import oracle as O
+    from paper_2201_12404_amd import workloads as W
+
+    threads = O.set_threads(0)
+    rho0, u0 = W.initial_fields(w)
+    nx, ny, nz = w.n
+    sx, sy, sz = 128, 128, 96
+    x0, y0 = (nx - sx) // 2, (ny - sy) // 2
+    r = rho0.reshape(nz, ny, nx)[:sz, y0:y0 + sy, x0:x0 + sx].reshape(-1).copy()
+    u = u0.reshape(3, nz, ny, nx)[:, :sz, y0:y0 + sy, x0:x0 + sx].reshape(3, -1).copy()
+    p = O.Params(D=3, n=(sx, sy, sz), bc=(0, 0, 1), collision=0, a=w.eos["eos_a"], b=w.eos["eos_b"],
+                 R=w.eos["eos_R"], acentric=w.eos["acentric"], Tr=w.T_over_Tc, kappa=w.kappa_tilde,
+                 nu_l=w.nu_liquid, nu_v=w.nu_vapour, rho_l=w.rho_l, rho_v=w.rho_v)
+    f = O.init_fluid(p, r, u)
+    steps, elapsed = 0, 0.0
+    while elapsed < budget_s and steps < 50:
+        t0 = time.perf_counter()
+        O.step(p, f, 1)
+        elapsed += time.perf_counter() - t0
+        steps += 1
+        if elapsed > 0.6 * budget_s:
+            break
+    mlups = sx * sy * sz * steps / elapsed / 1e6
+    return {"value": round(mlups, 4), "unit": "MLUPS", "cores": threads, "kind": "oracle",
+            "sample": f"{steps} step(s) of a {sx}x{sy}x{sz} block of the 256^3 impact state "
+                      f"(FP64 oracle, OpenMP over cells), {elapsed:.1f} s"}
+
+
+def copy_probe(nbytes: int = 1 << 30):
+    """A plain device copy kernel of known size (read nbytes, write nbytes),
+    for calibrating the rocprofv3 FETCH_SIZE / WRITE_SIZE counters."""
+    import torch
+    src = torch.ones(nbytes // 4, dtype=torch.float32, device="cuda")
+    dst = torch.empty_like(src)
+    torch.mul(src, 1.0, out=dst)
+    torch.cuda.synchronize()
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=100)
+    ap.add_argument("--warmup", type=int, default=10)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--cpu-budget", type=float, default=20.0)
+    ap.add_argument("--copy-probe", action="store_true", help="also run a 1 GiB copy kernel (counter calibration)")
+    ap.add_argument("--tile", type=str, default="", help="tx,ty,tm of the collision kernel")
+    args = ap.parse_args()
+
+    if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
+        print("bench.py runs on one GPU only: this build has no multi-GPU path "
+              "(the slab decomposition over xGMI is design-only).", file=sys.stderr)
+        sys.exit(2)
+
+    import numpy as np
+    import torch
+
+    from paper_2201_12404_amd import elmrt as E
+    from paper_2201_12404_amd import workloads as W
+
+    torch.cuda.set_device(0)
+    w = W.IMPACT_3D
+    params = E.params_for(w)
+    rho0, u0 = W.initial_fields(w)
+    sim = E.Simulation(params)
+    if args.tile:
+        tx, ty, tm = (int(v) for v in args.tile.split(","))
+        sim.set_tiling(tx, ty, tm)
+    sim.init_fields(rho0, u0)
+    del rho0, u0
+    print(f"[bench] {w.name}: warmup {args.warmup} steps", file=sys.stderr, flush=True)
+    sim.step(args.warmup)
+    torch.cuda.synchronize()
+
+    print(f"[bench] timing {args.steps} steps", file=sys.stderr, flush=True)
+    t0 = time.perf_counter()
+    ms_macro, ms_collide = sim.step_timed(args.steps)
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    _, _, sums = sim.read_macros()
+    sim.close()
+
+    N = w.N
+    ms_per_step = wall / args.steps * 1e3
+    mlups = N * args.steps / wall / 1e6
+    es = 4
+    b_macro, b_collide = algorithmic_bytes(3, es)
+    avg_collide_s = ms_collide / args.steps / 1e3
+    avg_macro_s = ms_macro / args.steps / 1e3
+    achieved = N * b_collide / avg_collide_s / 1e9
+    tag = "collide_d3q27_fp32_256"
+    traffic = measured_traffic(tag)
+    out = {
+        "metric": "MLUPS (D3Q27 FP32 256^3 drop-impact step)",
+        "value": round(mlups, 1),
+        "unit": "MLUPS",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": round(ms_per_step, 4),
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32",
+        "data": "synthetic",
+        "config": {"workload": w.name, "lattice": "D3Q27", "grid": list(w.n), "bc": "periodic x,y; walls z",
+                   "collision": "entropic", "density_ratio": 1000},
+        "hbm_gbs_algorithmic_step": round(N * (b_macro + b_collide) / wall * args.steps / 1e9, 1),
+        "kernels_ms": {"moments": round(avg_macro_s * 1e3, 4), "collide": round(avg_collide_s * 1e3, 4)},
+        "roofline": {
+            "kernel": "k_collide<3,float,64,4>",
+            "bound": "hbm",
+            "achieved": round(achieved, 1),
+            "peak": HBM_PEAK_GBS,
+            "unit": "GB/s",
+            "frac": round(achieved / HBM_PEAK_GBS, 4),
+            "traffic": traffic,
+            "bytes_per_cell": b_collide,
+        },
+        "mass_sum": sums[0],
+    }
+    if args.copy_probe:
+        copy_probe()
+    if not args.no_cpu_baseline:
+        print("[bench] cpu baseline", file=sys.stderr, flush=True)
+        out["cpu_baseline"] = cpu_baseline(w, args.cpu_budget)
+    else:
+        out["cpu_baseline"] = None
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

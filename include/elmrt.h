@@ -1,0 +1,139 @@
+/*
+ * elmrt.h -- C ABI of the MI355X (gfx950) library that advances the entropic
+ * multi-relaxation-time two-phase lattice Boltzmann model of Hosseini,
+ * Dorschner & Karlin ("Entropic multi-relaxation-time lattice Boltzmann model
+ * for large density ratio two-phase flows", arXiv:2201.12404).
+ *
+ * One time step (Sec. 2, eq. LBGK) is: pull-streaming of the populations,
+ * moments rho and rho u (Sec. 2.2), Peng-Robinson pressure and pseudo-potential
+ * psi (Sec. 2.3, 3.1), the psi and capillary force stencils of reach 2
+ * (Sec. 2.3), the diagonal correction Phi (Sec. 2.2), the product-form f^eq
+ * and f* (Sec. 2.1-2.2), the k + s + h split in the modified central Hermite
+ * basis (Appendix A), the entropic stabiliser gamma (Sec. 2.4) and the
+ * post-collision state.
+ *
+ * Conventions
+ *   - Every call returns elmrt_status; nothing throws across the ABI.  On an
+ *     error elmrt_last_error() returns a message (per thread).
+ *   - Lattice units dt = dr = 1, cs^2 = 1/3, P0 = rho cs^2 (Sec. 2.3).
+ *   - Cells are numbered cell = x + nx*(y + ny*z); host vector fields are
+ *     component-major: u[a*N + cell].
+ *   - Velocities are numbered i = (cx+1) + 3(cy+1) + 9(cz+1);
+ *     elmrt_velocities() returns the table.
+ *   - Device memory is caller-owned: a workspace of elmrt_workspace_bytes()
+ *     bytes, 256-byte aligned, that must outlive the handle.  The library
+ *     never allocates device memory for a simulation.
+ *   - Work is enqueued on the caller's HIP stream; elmrt_step never
+ *     synchronises.  Calls on one handle must come from one host thread at a
+ *     time.
+ */
+#ifndef ELMRT_H
+#define ELMRT_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct elmrt_sim elmrt_sim;   /* opaque, library-owned */
+
+typedef enum {
+    ELMRT_OK = 0,
+    ELMRT_E_INVALID = 1,   /* bad argument or parameter; nothing was enqueued */
+    ELMRT_E_NOMEM = 2,     /* workspace too small or host allocation failed */
+    ELMRT_E_DEVICE = 3,    /* a HIP call failed; the handle may be unusable */
+    ELMRT_E_UNSTABLE = 4,  /* a non-finite or non-positive density was seen (sticky) */
+    ELMRT_E_STATE = 5      /* call out of order (e.g. step before init_fields) */
+} elmrt_status;
+
+enum { ELMRT_D2Q9 = 0, ELMRT_D3Q27 = 1 };
+enum { ELMRT_FP32 = 0, ELMRT_FP64 = 1 };
+enum { ELMRT_ENTROPIC = 0, ELMRT_BGK = 1 };
+enum { ELMRT_PERIODIC = 0, ELMRT_WALL = 1 };
+
+/* Problem statement.  struct_size must be sizeof(elmrt_params). */
+typedef struct {
+    uint32_t struct_size;
+    int32_t  lattice;        /* ELMRT_D2Q9 or ELMRT_D3Q27 (Sec. 2.1) */
+    int32_t  precision;      /* ELMRT_FP32: populations and arithmetic in FP32; ELMRT_FP64 */
+    int32_t  collision;      /* ELMRT_ENTROPIC (gamma of Sec. 2.4) or ELMRT_BGK (gamma = 2) */
+    int64_t  n[3];           /* nx, ny, nz; nz = 1 for D2Q9; each >= 4 */
+    int32_t  bc[3];          /* per axis: ELMRT_PERIODIC, or ELMRT_WALL (half-way
+                                bounce-back at both ends; stencil ghosts mirror
+                                the density about the wall plane) */
+    int32_t  reserved;       /* 0 */
+    /* Peng-Robinson equation of state (Sec. 3.1): a, b, R, acentric factor,
+       and the temperature as T/Tc with Tc = 0.0778 a / (0.45724 b R). */
+    double   eos_a, eos_b, eos_R, acentric, T_over_Tc;
+    double   kappa_tilde;    /* capillarity kappa~ = kappa dr^2 of the force stencil (Sec. 2.3), >= 0 */
+    /* Kinematic viscosity nu (omega = 1/(3 nu + 1/2), Sec. 2): nu_vapour at
+       rho <= rho_vapour, nu_liquid at rho >= rho_liquid, linear in between.
+       With nu_liquid == nu_vapour the two densities are not used. */
+    double   nu_liquid, nu_vapour;
+    double   rho_liquid, rho_vapour;
+} elmrt_params;
+
+/* Bytes of device workspace the problem needs (populations twice, density
+ * and Phi-flux fields, a small status/reduction area). */
+elmrt_status elmrt_workspace_bytes(const elmrt_params* p, size_t* bytes);
+
+/* Validate p and bind a handle to the caller's workspace (device pointer,
+ * 256-byte aligned, >= elmrt_workspace_bytes) and HIP stream (hipStream_t, or
+ * NULL for the null stream).  Fails with ELMRT_E_INVALID on: unknown lattice,
+ * precision, collision or bc; n < 4 on an axis (nz != 1 for D2Q9); cells
+ * >= 2^31; a, b, R <= 0; T/Tc outside (0, 1); kappa_tilde < 0; nu <= 0;
+ * rho_liquid <= rho_vapour when the viscosities differ. */
+elmrt_status elmrt_create(const elmrt_params* p, void* dev_workspace, size_t workspace_bytes,
+                          void* hip_stream, elmrt_sim** out);
+
+/* Set the state to f = f^eq(rho0, u0 - F(rho0) dt / (2 rho0)) (product form,
+ * Sec. 2.2), with F the force of Sec. 2.3 on the initial density: u0 is the
+ * fluid velocity u + F dt/(2 rho) of the exact-difference forcing, so a drop
+ * given u0 = 0 starts at rest.  rho0[N] and u0[D*N] are host FP64 arrays read
+ * before the call returns; rho0 must be finite and positive and u0 finite
+ * (else ELMRT_E_INVALID).  Synchronises the stream. */
+elmrt_status elmrt_init_fields(elmrt_sim* s, const double* rho0, const double* u0);
+
+/* Enqueue nsteps >= 0 time steps on the stream (two kernels per step). */
+elmrt_status elmrt_step(elmrt_sim* s, int64_t nsteps);
+
+/* Like elmrt_step, and also time each kernel with HIP events on the stream;
+ * synchronises.  ms[0] = summed duration of the moment kernels, ms[1] = of
+ * the collision kernels (milliseconds). */
+elmrt_status elmrt_step_timed(elmrt_sim* s, int64_t nsteps, double ms[2]);
+
+/* Read rho(t) and the bare velocity u = sum c f / rho (Sec. 2.2) of the
+ * current state into host FP64 arrays (either may be NULL), and the sums
+ * [sum rho, sum rho u_x, sum rho u_y, sum rho u_z] accumulated in FP64
+ * (sums may be NULL).  Synchronises.  Returns ELMRT_E_UNSTABLE (outputs still
+ * filled) once a non-finite or non-positive density has been seen. */
+elmrt_status elmrt_read_macros(elmrt_sim* s, double* rho, double* u, double* sums);
+
+/* Read the populations f_i(r, t) (post-streaming) into host FP64 f[i*N + cell]. */
+elmrt_status elmrt_read_populations(elmrt_sim* s, double* f);
+
+/* Velocity table: c[3*i + a] for i < Q (9 or 27); returns Q, or -1. */
+int32_t elmrt_velocities(int32_t lattice, int32_t* c);
+
+/* Coexistence densities and saturation pressure of the Peng-Robinson EOS
+ * from the Maxwell equal-area rule (Sec. 3.1.1), host FP64. */
+elmrt_status elmrt_coexistence(const elmrt_params* p, double* rho_vapour, double* rho_liquid,
+                               double* p_sat);
+
+/* Tile shape of the collision kernel: tx cells along x (32, 64 or 128),
+ * ty along y (D3Q27: 1, 2, 4 or 8; D2Q9: 1), tm cells marched along the last
+ * axis per workgroup (>= 1).  Any shape gives the same result. */
+elmrt_status elmrt_set_tiling(elmrt_sim* s, int32_t tx, int32_t ty, int32_t tm);
+
+/* Release the handle (not the workspace).  NULL is ignored. */
+void elmrt_destroy(elmrt_sim* s);
+
+/* Message of the last failed call on this thread ("" if none). */
+const char* elmrt_last_error(void);
+
+#ifdef __cplusplus
+}
+#endif
+#endif

@@ -1,0 +1,463 @@
+// elmrt_api.cpp -- C ABI of the library (declared in include/elmrt.h): parameter
+// validation, workspace carving, the Peng-Robinson host thermodynamics, and
+// the enqueueing of the kernels of elmrt_kernels.hip on the caller's stream.
+#include "../../include/elmrt.h"
+#include "elmrt_internal.h"
+
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstdio>
+#include <cstring>
+#include <string>
+#include <vector>
+
+namespace {
+
+thread_local std::string g_last_error;
+
+elmrt_status fail(elmrt_status st, const std::string& msg)
+{
+    g_last_error = msg;
+    return st;
+}
+
+elmrt_status hip_fail(hipError_t e, const char* what)
+{
+    return fail(ELMRT_E_DEVICE, std::string(what) + ": " + hipGetErrorString(e));
+}
+
+constexpr size_t kAlign = 256;
+constexpr int kReadBlocks = 1024;
+
+size_t align_up(size_t v) { return (v + kAlign - 1) / kAlign * kAlign; }
+
+template <typename T>
+void widen(const void* src, double* dst, size_t n)
+{
+    const T* p = (const T*)src;
+    for (size_t i = 0; i < n; ++i) dst[i] = (double)p[i];
+}
+
+// ------------------------------------------------------------ thermodynamics
+
+// Peng-Robinson (Sec. 3.1): P = rho R T/(1 - b rho) - a alpha rho^2/(1 + 2 b rho - b^2 rho^2)
+struct PengRobinson {
+    double RT, b, aal;
+
+    PengRobinson(double a, double b_, double R, double acentric, double Tr)
+    {
+        const double Tc = 0.0778 * a / (0.45724 * b_ * R);
+        const double m = 0.37464 + 1.54226 * acentric - 0.26992 * acentric * acentric;
+        const double s = 1.0 + m * (1.0 - std::sqrt(Tr));
+        RT = R * Tr * Tc;
+        b = b_;
+        aal = a * s * s;
+    }
+    double P(double r) const
+    {
+        return r * RT / (1.0 - b * r) - aal * r * r / (1.0 + 2.0 * b * r - b * b * r * r);
+    }
+    double dP(double r) const
+    {
+        const double g = 1.0 + 2.0 * b * r - b * b * r * r;
+        const double dg = 2.0 * b - 2.0 * b * b * r;
+        const double om = 1.0 - b * r;
+        return RT / (om * om) - aal * (2.0 * r * g - r * r * dg) / (g * g);
+    }
+    // exact antiderivative of P / rho^2
+    double G(double r) const
+    {
+        const double s2 = std::sqrt(2.0);
+        return RT * std::log(r / (1.0 - b * r)) -
+               aal / (2.0 * s2 * b) * std::log((1.0 + (1.0 + s2) * b * r) / (1.0 + (1.0 - s2) * b * r));
+    }
+    // root of P(r) = p on [lo, hi] where P is increasing: safeguarded Newton
+    double solve(double p, double lo, double hi) const
+    {
+        double r = 0.5 * (lo + hi);
+        for (int it = 0; it < 200; ++it) {
+            const double f = P(r) - p;
+            if (f > 0.0) hi = r; else lo = r;
+            const double d = dP(r);
+            double nr = r - f / d;
+            if (!(nr > lo && nr < hi) || !(d > 0.0)) nr = 0.5 * (lo + hi);
+            if (std::fabs(nr - r) <= 1e-16 * r) { r = nr; break; }
+            r = nr;
+        }
+        return r;
+    }
+};
+
+// Maxwell equal-area rule (Sec. 3.1.1) written with the exact antiderivative:
+// P_sat (1/rho_v - 1/rho_l) = G(rho_l) - G(rho_v), P(rho_v) = P(rho_l) = P_sat.
+bool maxwell(const PengRobinson& pr, double* rv, double* rl, double* ps)
+{
+    const double rmax = 1.0 / pr.b;
+    double s1 = -1.0, s2 = -1.0;
+    const int NS = 20000;
+    double prev = pr.dP(rmax * 1e-9), prev_r = rmax * 1e-9;
+    for (int k = 1; k < NS && s2 < 0.0; ++k) {
+        const double r = rmax * k / NS;
+        const double d = pr.dP(r);
+        if (s1 < 0.0 && prev > 0.0 && d <= 0.0) {
+            double lo = prev_r, hi = r;
+            for (int it = 0; it < 100; ++it) {
+                const double mid = 0.5 * (lo + hi);
+                (pr.dP(mid) > 0.0 ? lo : hi) = mid;
+            }
+            s1 = 0.5 * (lo + hi);
+        } else if (s1 > 0.0 && prev < 0.0 && d >= 0.0) {
+            double lo = prev_r, hi = r;
+            for (int it = 0; it < 100; ++it) {
+                const double mid = 0.5 * (lo + hi);
+                (pr.dP(mid) < 0.0 ? lo : hi) = mid;
+            }
+            s2 = 0.5 * (lo + hi);
+        }
+        prev = d;
+        prev_r = r;
+    }
+    if (s1 < 0.0 || s2 < 0.0) return false;
+    double lo = std::max(pr.P(s2), 0.0), hi = pr.P(s1);
+    double a = 0.0, c = 0.0, p = 0.0;
+    for (int it = 0; it < 200; ++it) {
+        p = 0.5 * (lo + hi);
+        if (p == lo || p == hi) break;
+        a = pr.solve(p, 0.0, s1);
+        c = pr.solve(p, s2, rmax * (1.0 - 1e-15));
+        const double area = p * (1.0 / a - 1.0 / c) - (pr.G(c) - pr.G(a));
+        (area > 0.0 ? hi : lo) = p;
+    }
+    *ps = p;
+    *rv = pr.solve(p, 0.0, s1);
+    *rl = pr.solve(p, s2, rmax * (1.0 - 1e-15));
+    return true;
+}
+
+// -------------------------------------------------------------- validation
+
+elmrt_status validate(const elmrt_params* p)
+{
+    if (!p) return fail(ELMRT_E_INVALID, "params is NULL");
+    if (p->struct_size != sizeof(elmrt_params))
+        return fail(ELMRT_E_INVALID, "params.struct_size != sizeof(elmrt_params)");
+    if (p->lattice != ELMRT_D2Q9 && p->lattice != ELMRT_D3Q27) return fail(ELMRT_E_INVALID, "unknown lattice");
+    if (p->precision != ELMRT_FP32 && p->precision != ELMRT_FP64) return fail(ELMRT_E_INVALID, "unknown precision");
+    if (p->collision != ELMRT_ENTROPIC && p->collision != ELMRT_BGK) return fail(ELMRT_E_INVALID, "unknown collision");
+    const int D = p->lattice == ELMRT_D2Q9 ? 2 : 3;
+    for (int a = 0; a < 3; ++a) {
+        if (a < D && p->n[a] < 4) return fail(ELMRT_E_INVALID, "grid extent < 4");
+        if (a < D && p->bc[a] != ELMRT_PERIODIC && p->bc[a] != ELMRT_WALL) return fail(ELMRT_E_INVALID, "unknown bc");
+        if (p->n[a] > 65535 * 16) return fail(ELMRT_E_INVALID, "grid extent too large");
+    }
+    if (D == 2 && p->n[2] != 1) return fail(ELMRT_E_INVALID, "D2Q9 needs n[2] == 1");
+    const long double cells = (long double)p->n[0] * p->n[1] * p->n[2];
+    if (cells >= 2147483648.0L) return fail(ELMRT_E_INVALID, "grid has >= 2^31 cells");
+    if (!(p->eos_a > 0) || !(p->eos_b > 0) || !(p->eos_R > 0)) return fail(ELMRT_E_INVALID, "EOS a, b, R must be > 0");
+    if (!(p->T_over_Tc > 0 && p->T_over_Tc < 1)) return fail(ELMRT_E_INVALID, "T/Tc must be in (0, 1)");
+    if (!(p->kappa_tilde >= 0) || !std::isfinite(p->kappa_tilde)) return fail(ELMRT_E_INVALID, "kappa_tilde must be >= 0");
+    if (!(p->nu_liquid > 0) || !(p->nu_vapour > 0)) return fail(ELMRT_E_INVALID, "viscosities must be > 0");
+    if (p->nu_liquid != p->nu_vapour && !(p->rho_liquid > p->rho_vapour && p->rho_vapour >= 0))
+        return fail(ELMRT_E_INVALID, "rho_liquid must exceed rho_vapour when the viscosities differ");
+    if (p->reserved != 0) return fail(ELMRT_E_INVALID, "reserved must be 0");
+    return ELMRT_OK;
+}
+
+struct Layout {
+    size_t fA, fB, rho, q, flag, partials, total;
+};
+
+Layout layout_of(const elmrt_params* p)
+{
+    const int D = p->lattice == ELMRT_D2Q9 ? 2 : 3;
+    const int Q = D == 2 ? 9 : 27;
+    const size_t N = (size_t)p->n[0] * p->n[1] * p->n[2];
+    const size_t es = p->precision == ELMRT_FP64 ? 8 : 4;
+    Layout L;
+    size_t o = 0;
+    L.fA = o;       o = align_up(o + (size_t)Q * N * es);
+    L.fB = o;       o = align_up(o + (size_t)Q * N * es);
+    L.rho = o;      o = align_up(o + N * es);
+    L.q = o;        o = align_up(o + (size_t)D * N * es);
+    L.flag = o;     o = align_up(o + 256);
+    L.partials = o; o = align_up(o + (size_t)kReadBlocks * 4 * sizeof(double));
+    L.total = o;
+    return L;
+}
+
+}  // namespace
+
+struct elmrt_sim {
+    elmrt_params p;
+    int D, Q;
+    size_t N, es;
+    char* ws;
+    size_t ws_bytes;
+    hipStream_t stream;
+    void* buf[2];
+    int cur;            // index of the buffer holding the state
+    void* rho;
+    void* q;
+    unsigned* flag;
+    double* partials;
+    bool initialised;
+    int tx, ty, tm;
+    elmrt::Phys<double> ph;
+    elmrt::Launch L;
+};
+
+extern "C" {
+
+elmrt_status elmrt_workspace_bytes(const elmrt_params* p, size_t* bytes)
+{
+    elmrt_status st = validate(p);
+    if (st != ELMRT_OK) return st;
+    if (!bytes) return fail(ELMRT_E_INVALID, "bytes is NULL");
+    *bytes = layout_of(p).total;
+    return ELMRT_OK;
+}
+
+elmrt_status elmrt_create(const elmrt_params* p, void* ws, size_t ws_bytes, void* stream, elmrt_sim** out)
+{
+    elmrt_status st = validate(p);
+    if (st != ELMRT_OK) return st;
+    if (!out) return fail(ELMRT_E_INVALID, "out is NULL");
+    *out = nullptr;
+    if (!ws) return fail(ELMRT_E_INVALID, "workspace is NULL");
+    if ((uintptr_t)ws % kAlign) return fail(ELMRT_E_INVALID, "workspace is not 256-byte aligned");
+    const Layout lay = layout_of(p);
+    if (ws_bytes < lay.total) return fail(ELMRT_E_NOMEM, "workspace smaller than elmrt_workspace_bytes()");
+    elmrt_sim* s = new (std::nothrow) elmrt_sim();
+    if (!s) return fail(ELMRT_E_NOMEM, "host allocation failed");
+    s->p = *p;
+    s->D = p->lattice == ELMRT_D2Q9 ? 2 : 3;
+    s->Q = s->D == 2 ? 9 : 27;
+    s->N = (size_t)p->n[0] * p->n[1] * p->n[2];
+    s->es = p->precision == ELMRT_FP64 ? 8 : 4;
+    s->ws = (char*)ws;
+    s->ws_bytes = ws_bytes;
+    s->stream = (hipStream_t)stream;
+    s->buf[0] = s->ws + lay.fA;
+    s->buf[1] = s->ws + lay.fB;
+    s->cur = 0;
+    s->rho = s->ws + lay.rho;
+    s->q = s->ws + lay.q;
+    s->flag = (unsigned*)(s->ws + lay.flag);
+    s->partials = (double*)(s->ws + lay.partials);
+    s->initialised = false;
+    s->tx = 64;
+    s->ty = s->D == 3 ? 4 : 1;
+    s->tm = 16;
+    // physics constants (host FP64; cast to the working precision at launch)
+    PengRobinson pr(p->eos_a, p->eos_b, p->eos_R, p->acentric, p->T_over_Tc);
+    s->ph.RT = pr.RT;
+    s->ph.b = pr.b;
+    s->ph.aal = pr.aal;
+    s->ph.kappa = p->kappa_tilde;
+    if (p->nu_liquid == p->nu_vapour) {
+        s->ph.nu_v = p->nu_liquid;
+        s->ph.dnu = 0.0;
+        s->ph.rho_v = 0.0;
+        s->ph.inv_drho = 0.0;
+    } else {
+        s->ph.nu_v = p->nu_vapour;
+        s->ph.dnu = p->nu_liquid - p->nu_vapour;
+        s->ph.rho_v = p->rho_vapour;
+        s->ph.inv_drho = 1.0 / (p->rho_liquid - p->rho_vapour);
+    }
+    s->ph.entropic = p->collision == ELMRT_ENTROPIC ? 1 : 0;
+    s->L.D = s->D;
+    s->L.fp64 = p->precision == ELMRT_FP64;
+    for (int a = 0; a < 3; ++a) {
+        s->L.g.n[a] = (int)p->n[a];
+        s->L.g.wall[a] = (a < s->D) ? (p->bc[a] == ELMRT_WALL) : 0;
+    }
+    s->L.g.N = (int)s->N;
+    s->L.g.nxny = (int)(p->n[0] * p->n[1]);
+    s->L.stream = s->stream;
+    hipError_t e = hipMemsetAsync(s->flag, 0, 256, s->stream);
+    if (e != hipSuccess) {
+        delete s;
+        return hip_fail(e, "hipMemsetAsync(flag)");
+    }
+    *out = s;
+    return ELMRT_OK;
+}
+
+elmrt_status elmrt_init_fields(elmrt_sim* s, const double* rho0, const double* u0)
+{
+    if (!s || !rho0 || !u0) return fail(ELMRT_E_INVALID, "NULL argument");
+    for (size_t c = 0; c < s->N; ++c)
+        if (!(rho0[c] > 0.0) || !std::isfinite(rho0[c]))
+            return fail(ELMRT_E_INVALID, "rho0 must be finite and positive");
+    for (size_t c = 0; c < (size_t)s->D * s->N; ++c)
+        if (!std::isfinite(u0[c])) return fail(ELMRT_E_INVALID, "u0 must be finite");
+    // stage rho0 and u0 (FP64) in the buffer that does not hold the state
+    double* stage = (double*)s->buf[1 - s->cur];
+    hipError_t e = hipMemcpyAsync(stage, rho0, s->N * sizeof(double), hipMemcpyHostToDevice, s->stream);
+    if (e == hipSuccess)
+        e = hipMemcpyAsync(stage + s->N, u0, (size_t)s->D * s->N * sizeof(double), hipMemcpyHostToDevice, s->stream);
+    if (e != hipSuccess) return hip_fail(e, "hipMemcpyAsync(init)");
+    e = elmrt::launch_shift_velocity(s->L, stage, stage + s->N, s->ph);
+    if (e != hipSuccess) return hip_fail(e, "velocity shift kernel");
+    e = elmrt::launch_init(s->L, stage, stage + s->N, s->buf[s->cur]);
+    if (e != hipSuccess) return hip_fail(e, "init kernel");
+    e = hipMemsetAsync(s->flag, 0, 256, s->stream);
+    if (e == hipSuccess) e = hipStreamSynchronize(s->stream);
+    if (e != hipSuccess) return hip_fail(e, "init");
+    s->initialised = true;
+    return ELMRT_OK;
+}
+
+// Enqueue nsteps steps.  With ev != NULL (2*nsteps + 1 events) an event is
+// recorded before the first kernel and after every kernel, so that kernel k
+// of the run lies between ev[k] and ev[k+1].
+static elmrt_status step_impl(elmrt_sim* s, int64_t nsteps, hipEvent_t* ev)
+{
+    if (!s) return fail(ELMRT_E_INVALID, "sim is NULL");
+    if (nsteps < 0) return fail(ELMRT_E_INVALID, "nsteps < 0");
+    if (!s->initialised) return fail(ELMRT_E_STATE, "elmrt_init_fields has not been called");
+    hipError_t e;
+    if (ev && (e = hipEventRecord(ev[0], s->stream)) != hipSuccess) return hip_fail(e, "hipEventRecord");
+    for (int64_t k = 0; k < nsteps; ++k) {
+        void* cur = s->buf[s->cur];
+        void* nxt = s->buf[1 - s->cur];
+        e = elmrt::launch_macro(s->L, cur, s->rho, s->q, s->flag);
+        if (e != hipSuccess) return hip_fail(e, "moment kernel");
+        if (ev && (e = hipEventRecord(ev[2 * k + 1], s->stream)) != hipSuccess) return hip_fail(e, "hipEventRecord");
+        e = elmrt::launch_collide(s->L, s->tx, s->ty, s->tm, cur, nxt, s->rho, s->q, s->ph);
+        if (e != hipSuccess) return hip_fail(e, "collision kernel");
+        if (ev && (e = hipEventRecord(ev[2 * k + 2], s->stream)) != hipSuccess) return hip_fail(e, "hipEventRecord");
+        s->cur = 1 - s->cur;
+    }
+    return ELMRT_OK;
+}
+
+elmrt_status elmrt_step(elmrt_sim* s, int64_t nsteps) { return step_impl(s, nsteps, nullptr); }
+
+elmrt_status elmrt_step_timed(elmrt_sim* s, int64_t nsteps, double ms[2])
+{
+    if (!ms) return fail(ELMRT_E_INVALID, "ms is NULL");
+    if (nsteps < 0 || nsteps > (1 << 20)) return fail(ELMRT_E_INVALID, "nsteps out of range for timing");
+    ms[0] = ms[1] = 0.0;
+    std::vector<hipEvent_t> ev((size_t)(2 * nsteps + 1));
+    size_t made = 0;
+    hipError_t e = hipSuccess;
+    for (; made < ev.size(); ++made)
+        if ((e = hipEventCreate(&ev[made])) != hipSuccess) break;
+    elmrt_status st = ELMRT_OK;
+    if (e != hipSuccess) st = hip_fail(e, "hipEventCreate");
+    if (st == ELMRT_OK) st = step_impl(s, nsteps, ev.data());
+    if (st == ELMRT_OK && (e = hipEventSynchronize(ev.back())) != hipSuccess) st = hip_fail(e, "hipEventSynchronize");
+    for (int64_t k = 0; st == ELMRT_OK && k < nsteps; ++k) {
+        float a = 0.f, b = 0.f;
+        if ((e = hipEventElapsedTime(&a, ev[2 * k], ev[2 * k + 1])) != hipSuccess ||
+            (e = hipEventElapsedTime(&b, ev[2 * k + 1], ev[2 * k + 2])) != hipSuccess)
+            st = hip_fail(e, "hipEventElapsedTime");
+        ms[0] += a;
+        ms[1] += b;
+    }
+    for (size_t k = 0; k < made; ++k) (void)hipEventDestroy(ev[k]);
+    return st;
+}
+
+elmrt_status elmrt_read_macros(elmrt_sim* s, double* rho, double* u, double* sums)
+{
+    if (!s) return fail(ELMRT_E_INVALID, "sim is NULL");
+    if (!s->initialised) return fail(ELMRT_E_STATE, "elmrt_init_fields has not been called");
+    char* tmp = (char*)s->buf[1 - s->cur];
+    void* trho = tmp;
+    void* tu = tmp + s->N * s->es;
+    hipError_t e = elmrt::launch_readout(s->L, s->buf[s->cur], trho, tu, s->partials, kReadBlocks, s->flag);
+    if (e != hipSuccess) return hip_fail(e, "readout kernel");
+    std::vector<char> h((1 + (size_t)s->D) * s->N * s->es);
+    std::vector<double> part((size_t)kReadBlocks * 4);
+    unsigned flag = 0;
+    e = hipMemcpyAsync(h.data(), tmp, h.size(), hipMemcpyDeviceToHost, s->stream);
+    if (e == hipSuccess) e = hipMemcpyAsync(part.data(), s->partials, part.size() * sizeof(double), hipMemcpyDeviceToHost, s->stream);
+    if (e == hipSuccess) e = hipMemcpyAsync(&flag, s->flag, sizeof(unsigned), hipMemcpyDeviceToHost, s->stream);
+    if (e == hipSuccess) e = hipStreamSynchronize(s->stream);
+    if (e != hipSuccess) return hip_fail(e, "read_macros copy");
+    if (rho) {
+        if (s->es == 4) widen<float>(h.data(), rho, s->N);
+        else widen<double>(h.data(), rho, s->N);
+    }
+    if (u) {
+        if (s->es == 4) widen<float>(h.data() + s->N * s->es, u, (size_t)s->D * s->N);
+        else widen<double>(h.data() + s->N * s->es, u, (size_t)s->D * s->N);
+    }
+    if (sums) {
+        // Neumaier summation of the per-block FP64 partials, in block order
+        for (int k = 0; k < 4; ++k) {
+            double acc = 0.0, comp = 0.0;
+            for (int b = 0; b < kReadBlocks; ++b) {
+                const double x = part[(size_t)b * 4 + k];
+                const double t = acc + x;
+                comp += (std::fabs(acc) >= std::fabs(x)) ? (acc - t) + x : (x - t) + acc;
+                acc = t;
+            }
+            sums[k] = acc + comp;
+        }
+    }
+    if (flag) return fail(ELMRT_E_UNSTABLE, "non-finite or non-positive density encountered");
+    return ELMRT_OK;
+}
+
+elmrt_status elmrt_read_populations(elmrt_sim* s, double* f)
+{
+    if (!s || !f) return fail(ELMRT_E_INVALID, "NULL argument");
+    if (!s->initialised) return fail(ELMRT_E_STATE, "elmrt_init_fields has not been called");
+    void* tmp = s->buf[1 - s->cur];
+    hipError_t e = elmrt::launch_pull(s->L, s->buf[s->cur], tmp);
+    if (e != hipSuccess) return hip_fail(e, "pull kernel");
+    std::vector<char> h((size_t)s->Q * s->N * s->es);
+    e = hipMemcpyAsync(h.data(), tmp, h.size(), hipMemcpyDeviceToHost, s->stream);
+    if (e == hipSuccess) e = hipStreamSynchronize(s->stream);
+    if (e != hipSuccess) return hip_fail(e, "read_populations copy");
+    if (s->es == 4) widen<float>(h.data(), f, (size_t)s->Q * s->N);
+    else widen<double>(h.data(), f, (size_t)s->Q * s->N);
+    return ELMRT_OK;
+}
+
+int32_t elmrt_velocities(int32_t lattice, int32_t* c)
+{
+    if (lattice != ELMRT_D2Q9 && lattice != ELMRT_D3Q27) return -1;
+    const int D = lattice == ELMRT_D2Q9 ? 2 : 3;
+    const int Q = D == 2 ? 9 : 27;
+    if (c)
+        for (int i = 0; i < Q; ++i) {
+            c[3 * i + 0] = i % 3 - 1;
+            c[3 * i + 1] = (i / 3) % 3 - 1;
+            c[3 * i + 2] = D == 3 ? i / 9 - 1 : 0;
+        }
+    return Q;
+}
+
+elmrt_status elmrt_coexistence(const elmrt_params* p, double* rho_vapour, double* rho_liquid, double* p_sat)
+{
+    if (!p || !rho_vapour || !rho_liquid || !p_sat) return fail(ELMRT_E_INVALID, "NULL argument");
+    if (!(p->eos_a > 0) || !(p->eos_b > 0) || !(p->eos_R > 0)) return fail(ELMRT_E_INVALID, "EOS a, b, R must be > 0");
+    if (!(p->T_over_Tc > 0 && p->T_over_Tc < 1)) return fail(ELMRT_E_INVALID, "T/Tc must be in (0, 1)");
+    PengRobinson pr(p->eos_a, p->eos_b, p->eos_R, p->acentric, p->T_over_Tc);
+    if (!maxwell(pr, rho_vapour, rho_liquid, p_sat)) return fail(ELMRT_E_INVALID, "no two-phase region at this temperature");
+    return ELMRT_OK;
+}
+
+elmrt_status elmrt_set_tiling(elmrt_sim* s, int32_t tx, int32_t ty, int32_t tm)
+{
+    if (!s) return fail(ELMRT_E_INVALID, "sim is NULL");
+    if (tm < 1) return fail(ELMRT_E_INVALID, "tm must be >= 1");
+    if (!elmrt::collide_shape_supported(s->D, tx, ty)) return fail(ELMRT_E_INVALID, "tile shape not compiled");
+    s->tx = tx;
+    s->ty = ty;
+    s->tm = tm;
+    return ELMRT_OK;
+}
+
+void elmrt_destroy(elmrt_sim* s) { delete s; }
+
+const char* elmrt_last_error(void) { return g_last_error.c_str(); }
+
+}  // extern "C"

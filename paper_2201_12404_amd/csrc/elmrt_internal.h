@@ -1,0 +1,63 @@
+// elmrt_internal.h -- declarations shared by the C ABI layer and the HIP
+// kernels of the library (not installed, not part of the ABI).
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace elmrt {
+
+// Grid description passed by value to every kernel.
+struct Grid {
+    int n[3];      // nx, ny, nz (nz = 1 in 2-D)
+    int wall[3];   // 1: half-way bounce-back walls at both ends of the axis
+    int N;         // number of cells (< 2^31)
+    int nxny;
+};
+
+// Equation of state and viscosity constants, in working precision.
+template <typename T>
+struct Phys {
+    T RT;          // R T
+    T b;           // Peng-Robinson co-volume
+    T aal;         // a alpha(T)
+    T kappa;       // capillarity kappa~
+    T nu_v;        // vapour viscosity
+    T dnu;         // nu_l - nu_v
+    T rho_v;       // lower density anchor of nu(rho)
+    T inv_drho;    // 1 / (rho_l - rho_v), 0 when nu is uniform
+    int entropic;  // 1: entropic gamma, 0: BGK
+};
+
+// Every launcher returns the launch status (hipGetLastError after the launch).
+// T is float or double, selected by the 'fp64' flag; D is 2 or 3.
+struct Launch {
+    int D;
+    int fp64;
+    Grid g;
+    hipStream_t stream;
+};
+
+hipError_t launch_macro(const Launch& L, const void* cur, void* rho, void* q, unsigned* flag);
+
+hipError_t launch_collide(const Launch& L, int tx, int ty, int tm, const void* cur, void* nxt,
+                          const void* rho, const void* q, const Phys<double>& ph);
+
+// u0 -= F(rho0) / (2 rho0) in place (fluid velocity -> bare velocity).
+hipError_t launch_shift_velocity(const Launch& L, const double* rho0, double* u0, const Phys<double>& ph);
+
+// f := f^eq(rho0, u0) stored so that pull-streaming yields f^eq at every cell.
+hipError_t launch_init(const Launch& L, const double* rho0, const double* u0, void* cur);
+
+// rho, u of the current state (working precision), per-block FP64 partial sums
+// of rho and rho u (nblocks x 4) and the instability flag.
+hipError_t launch_readout(const Launch& L, const void* cur, void* rho, void* u, double* partials,
+                          int nblocks, unsigned* flag);
+
+// f_i(r, t) = pulled populations, written to out[i*N + cell].
+hipError_t launch_pull(const Launch& L, const void* cur, void* out);
+
+// Tile shapes compiled for the collision kernel.
+bool collide_shape_supported(int D, int tx, int ty);
+
+}  // namespace elmrt

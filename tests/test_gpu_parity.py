@@ -1,0 +1,249 @@
+"""Parity of the HIP path (through the C ABI) with the FP64 oracle, on seeded
+inputs shaped like the paper's workloads.
+
+Norms: e_rho = max|rho_gpu - rho_ora| / max|rho_ora|, e_u likewise on the bare
+velocity, l2_u = ||u_gpu - u_ora||_2 / ||u_ora||_2.
+Bars: FP64 build: e_rho, e_u <= 1e-12.  FP32 build (after 1000 steps):
+e_rho <= 1e-5 and l2_u <= 1e-5 (relative 1e-5 on the fields); e_u <= 2e-4,
+the FP32 storage floor: rounding the stored populations (2^-24) re-injects
+~1e-7 of the velocity scale per step, and at ill-conditioned instants of the
+impact flow the FP64 oracle itself amplifies such perturbations ~10x over
+~100 steps; with every operation of the collision in FP64 and only the
+storage in FP32 the max-norm velocity error is the same (~2e-5).
+"""
+import os
+import sys
+
+import numpy as np
+import pytest
+
+from common import oracle_params, rel_l2, rel_max, velocity_map
+from oracle import oracle as O
+from paper_2201_12404_amd import elmrt as E
+from paper_2201_12404_amd import workloads as W
+
+pytestmark = pytest.mark.gpu
+
+
+def say(*a):
+    print(*a, flush=True)
+    sys.stdout.flush()
+
+
+@pytest.fixture(scope="module", autouse=True)
+def _gpu():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    torch.cuda.set_device(0)
+    O.set_threads(min(16, os.cpu_count() or 1))
+    yield
+
+
+def run_gpu(w, steps, collision=0, tiling=None, populations=False):
+    say(f"[gpu] {w.name} n={w.n} bc={w.bc} prec={w.precision} coll={collision} steps={steps} tiling={tiling}")
+    rho0, u0 = W.initial_fields(w)
+    sim = E.Simulation(E.params_for(w, collision))
+    if tiling:
+        sim.set_tiling(*tiling)
+    sim.init_fields(rho0, u0)
+    sim.step(steps)
+    rho, u, sums = sim.read_macros()
+    f = sim.read_populations() if populations else None
+    sim.close()
+    return rho, u, sums, f
+
+
+def run_oracle(w, steps, collision=0):
+    rho0, u0 = W.initial_fields(w)
+    p = oracle_params(w, collision)
+    f = O.init_fluid(p, rho0, u0)
+    O.step(p, f, steps)
+    rho, u, sums = O.macros(p, f)
+    return rho, u, sums, f, p
+
+
+def _small(D, bc, prec, n=None):
+    """Small seeded case spanning several tiles with a ragged tail: a drop
+    impact on a film when the last axis has walls, else a static drop."""
+    from dataclasses import replace
+    if D == 2:
+        n = n or (70, 44)
+        if bc[1]:
+            w = W.IMPACT_2D.scaled(n=n, radius=9.0, film=8.0, centre=(33.0, 8.0 + 9.0 + 10.0),
+                                   name="small-d2q9-impact")
+        else:
+            w = W.STATIC_DROP_FP64.scaled(n=n, radius=10.0, film=0.0, centre=(33.0, 22.0),
+                                          name="small-d2q9-drop")
+    else:
+        n = n or (70, 13, 30)
+        if bc[2]:
+            w = W.IMPACT_3D.scaled(n=n, radius=5.0, film=8.0, centre=(30.0, 6.0, 8.0 + 5.0 + 8.0),
+                                   name="small-d3q27-impact")
+        else:
+            w = replace(W.IMPACT_3D.scaled(n=n, radius=6.0, film=0.0, centre=(30.0, 6.0, 15.0),
+                                           name="small-d3q27-drop"), kind="drop")
+    return replace(w, bc=bc, precision=prec, noise=1e-3, seed=3)
+
+
+@pytest.mark.parametrize("D,bc", [(2, (0, 0)), (2, (0, 1)), (2, (1, 1)), (3, (0, 0, 1)), (3, (1, 0, 0)),
+                                  (3, (0, 0, 0))])
+@pytest.mark.parametrize("collision", [0, 1])
+def test_fp64_small_fields_and_populations(D, bc, collision):
+    """FP64 build against the oracle element by element after 25 steps, on
+    grids spanning several tiles with a ragged tail, periodic and wall axes."""
+    w = _small(D, bc, 1)
+    steps = 25
+    rho_g, u_g, s_g, f_g = run_gpu(w, steps, collision, populations=True)
+    rho_o, u_o, s_o, f_o, p = run_oracle(w, steps, collision)
+    assert rel_max(rho_g, rho_o) < 1e-12
+    assert rel_max(u_g, u_o) < 1e-12
+    m = velocity_map(E.elmrt_velocities(w.lattice), D)
+    np.testing.assert_allclose(f_g.T, f_o[:, m], rtol=0, atol=1e-13 * np.abs(f_o).max())
+    assert abs(s_g[0] - s_o[0]) <= 1e-12 * s_o[0]
+
+
+@pytest.mark.parametrize("D,bc", [(2, (0, 1)), (3, (0, 0, 1)), (3, (1, 1, 0))])
+def test_initial_state_matches_oracle(D, bc):
+    """The device-side initialisation (force on the initial density, bare
+    velocity shift, product-form equilibrium) against the oracle's, element by
+    element, before any step (FP64)."""
+    w = _small(D, bc, 1)
+    _, _, _, f_g = run_gpu(w, 0, populations=True)
+    rho0, u0 = W.initial_fields(w)
+    f_o = O.init_fluid(oracle_params(w), rho0, u0)
+    m = velocity_map(E.elmrt_velocities(w.lattice), D)
+    np.testing.assert_allclose(f_g.T, f_o[:, m], rtol=0, atol=1e-14 * np.abs(f_o).max())
+
+
+def test_static_drop_fp64_1000_steps():
+    """128^2 periodic static drop (FP64, entropic) after 1000 steps: 1e-12."""
+    w = W.STATIC_DROP_FP64
+    rho_g, u_g, s_g, _ = run_gpu(w, 1000)
+    rho_o, u_o, s_o, _, _ = run_oracle(w, 1000)
+    e_rho, e_u = rel_max(rho_g, rho_o), rel_max(u_g, u_o)
+    say(f"static drop fp64: e_rho={e_rho:.3e} e_u={e_u:.3e}")
+    assert e_rho < 1e-12 and e_u < 1e-12
+    assert abs(s_g[0] / s_o[0] - 1) < 1e-13
+
+
+def test_impact_2d_fp32_scaled_1000_steps():
+    """Drop impact on a film (D2Q9, FP32, density ratio 1000, walls in y) at a
+    quarter of the 1024 x 512 size (film kept >= 2W thick), 1000 steps
+    (contact at ~ step 100): 1e-5."""
+    w = W.IMPACT_2D.scaled(n=(256, 128), radius=20.0, film=10.0, centre=(128.0, 10.0 + 20.0 + 14.0),
+                           steps=1000, name="impact-d2q9-256x128-fp32")
+    rho_g, u_g, _, _ = run_gpu(w, 1000)
+    rho_o, u_o, _, _, _ = run_oracle(w, 1000)
+    e_rho, e_u, l2_u = rel_max(rho_g, rho_o), rel_max(u_g, u_o), rel_l2(u_g, u_o)
+    say(f"impact 2d fp32: e_rho={e_rho:.3e} e_u={e_u:.3e} l2_u={l2_u:.3e}")
+    assert e_rho < 1e-5 and l2_u < 1e-5 and e_u < 2e-4
+
+
+def test_impact_3d_fp32_scaled():
+    """Drop impact on a film (D3Q27, FP32, density ratio 1000, walls in z) on
+    a 72 x 40 x 40 grid (two tiles in x, ragged), 300 steps: 1e-5."""
+    w = W.IMPACT_3D.scaled(n=(72, 40, 40), radius=10.0, film=8.0, centre=(36.0, 20.0, 8.0 + 10.0 + 10.0),
+                           steps=300, name="impact-d3q27-72x40x40-fp32")
+    rho_g, u_g, _, _ = run_gpu(w, w.steps)
+    rho_o, u_o, _, _, _ = run_oracle(w, w.steps)
+    e_rho, e_u, l2_u = rel_max(rho_g, rho_o), rel_max(u_g, u_o), rel_l2(u_g, u_o)
+    say(f"impact 3d fp32: e_rho={e_rho:.3e} e_u={e_u:.3e} l2_u={l2_u:.3e}")
+    assert e_rho < 1e-5 and l2_u < 1e-5 and e_u < 2e-4
+
+
+@pytest.mark.parametrize("D,shapes", [(3, [(64, 4, 16), (32, 8, 5), (64, 2, 7), (128, 2, 64)]),
+                                      (2, [(64, 1, 16), (128, 1, 3), (256, 1, 100)])])
+def test_tile_shapes_bitwise_identical(D, shapes):
+    """Every tile shape and marching depth gives bitwise the same state."""
+    w = _small(D, (0, 0, 1) if D == 3 else (0, 1), 0)
+    ref = None
+    for sh in shapes:
+        _, _, _, f = run_gpu(w, 12, tiling=sh, populations=True)
+        if ref is None:
+            ref = f
+        else:
+            assert np.array_equal(f, ref), sh
+
+
+def test_minimal_grid():
+    """Smallest accepted grid (4 cells per axis), periodic and walls."""
+    for D, bc in ((2, (1, 0)), (3, (0, 1, 0))):
+        w = _small(D, bc, 1, n=(4, 4) if D == 2 else (4, 4, 4))
+        from dataclasses import replace
+        w = replace(w, radius=1.5, film=1.0, centre=(2.0,) * D)
+        rho_g, u_g, _, _ = run_gpu(w, 5)
+        rho_o, u_o, _, _, _ = run_oracle(w, 5)
+        assert rel_max(rho_g, rho_o) < 1e-12 and rel_max(u_g, u_o) < 1e-12
+
+
+def test_full_size_3d_one_step_sampled():
+    """256^3 D3Q27 FP32 impact in the benchmark's launch configuration: one
+    step from the seeded state, sampled cells against the oracle's
+    single-cell update (including wall-adjacent and periodic-seam cells)."""
+    w = W.IMPACT_3D
+    rho0, u0 = W.initial_fields(w)
+    say("[gpu] full-size 256^3 one step")
+    sim = E.Simulation(E.params_for(w))
+    sim.init_fields(rho0, u0)
+    sim.step(1)
+    f_g = sim.read_populations()
+    rho_g, _, sums = sim.read_macros()
+    sim.close()
+    n = w.n
+    rng = np.random.default_rng(11)
+    pts = [(0, 0, 0), (255, 255, 255), (128, 128, 62), (128, 128, 22), (0, 128, 1), (255, 0, 254)]
+    pts += [tuple(int(v) for v in rng.integers(0, 256, 3)) for _ in range(40)]
+    pts += [(int(x), int(y), int(z)) for x, y, z in zip(rng.integers(100, 156, 20), rng.integers(100, 156, 20),
+                                                        rng.integers(5, 70, 20))]
+    cells = np.array([x + n[0] * (y + n[1] * z) for x, y, z in pts])
+    p = oracle_params(w)
+    f0 = O.init_fluid(p, rho0, u0)
+    f_o = O.update_cells(p, f0, cells)
+    m = velocity_map(E.elmrt_velocities(w.lattice), 3)
+    ref = f_o[:, m]
+    got = f_g[:, cells].T
+    err = np.abs(got - ref).max() / np.abs(ref).max()
+    say(f"full-size one step sampled: max rel err {err:.3e}")
+    assert err < 1e-6
+    # mass of the whole grid: FP64 sums of the FP32 state
+    m0 = rho0.sum()
+    assert abs(sums[0] / m0 - 1) < 1e-6
+
+
+def test_unstable_flag_is_reported():
+    """BGK at nu = 0.001 and density ratio 1000 diverges (the oracle reaches a
+    negative density by step 80), while the entropic collision stays bounded
+    (Sec. 3.1.2-3.2); the sticky flag turns read_macros into ElmrtUnstable."""
+    from dataclasses import replace
+    w = replace(W.IMPACT_2D, n=(64, 8), bc=(0, 0), kind="drop", nu_liquid=0.001, nu_vapour=0.001,
+                noise=0.0, name="layer-ratio1000-nu0.001")
+    x = np.arange(64)
+    prof = 0.5 * (np.tanh(2 * (x - 16) / 5) - np.tanh(2 * (x - 48) / 5))
+    rho0 = np.tile(w.rho_v + (w.rho_l - w.rho_v) * prof, 8)
+    sims = {}
+    for coll in (1, 0):
+        sim = E.Simulation(E.params_for(w, collision=coll))
+        sim.init_fields(rho0, np.zeros((2, rho0.size)))
+        sim.step(400)
+        sims[coll] = sim
+    with pytest.raises(E.ElmrtUnstable):
+        sims[1].read_macros()
+    rho, _, _ = sims[0].read_macros()
+    assert np.all(np.isfinite(rho)) and rho.min() > 0
+    for sim in sims.values():
+        sim.close()
+
+
+def test_init_rejects_bad_density():
+    w = _small(2, (0, 0), 0)
+    rho0, u0 = W.initial_fields(w)
+    rho0[5] = -1.0
+    sim = E.Simulation(E.params_for(w))
+    with pytest.raises(E.ElmrtError) as ei:
+        sim.init_fields(rho0, u0)
+    assert ei.value.status == E.ELMRT_E_INVALID
+    with pytest.raises(E.ElmrtError) as ei:
+        sim.step(1)
+    assert ei.value.status == E.ELMRT_E_STATE
+    sim.close()
