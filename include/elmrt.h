@@ -57,7 +57,11 @@ enum { ELMRT_PERIODIC = 0, ELMRT_WALL = 1 };
 typedef struct {
     uint32_t struct_size;
     int32_t  lattice;        /* ELMRT_D2Q9 or ELMRT_D3Q27 (Sec. 2.1) */
-    int32_t  precision;      /* ELMRT_FP32: populations and arithmetic in FP32; ELMRT_FP64 */
+    int32_t  precision;      /* ELMRT_FP32: populations, density and fluxes stored in FP32;
+                                per-cell scalars (moments, EOS, force sums, f^eq, f*) are
+                                formed in FP64 registers, the small non-equilibrium terms
+                                in FP32, one rounding per stored population.
+                                ELMRT_FP64: storage and arithmetic in FP64. */
     int32_t  collision;      /* ELMRT_ENTROPIC (gamma of Sec. 2.4) or ELMRT_BGK (gamma = 2) */
     int64_t  n[3];           /* nx, ny, nz; nz = 1 for D2Q9; each >= 4 */
     int32_t  bc[3];          /* per axis: ELMRT_PERIODIC, or ELMRT_WALL (half-way
@@ -122,9 +126,11 @@ int32_t elmrt_velocities(int32_t lattice, int32_t* c);
 elmrt_status elmrt_coexistence(const elmrt_params* p, double* rho_vapour, double* rho_liquid,
                                double* p_sat);
 
-/* Tile shape of the collision kernel: tx cells along x (32, 64 or 128),
- * ty along y (D3Q27: 1, 2, 4 or 8; D2Q9: 1), tm cells marched along the last
- * axis per workgroup (>= 1).  Any shape gives the same result. */
+/* Tile shape of the collision kernel: tx x ty cells per workgroup, marched
+ * over tm (>= 1) planes along the last axis.  Compiled shapes:
+ * D2Q9 ty = 1 with tx = 64, 128 or 256; D3Q27 (tx, ty) = (64, 4), (64, 2),
+ * (32, 8) or (128, 2).  Other shapes return ELMRT_E_INVALID and leave the
+ * tiling unchanged.  Every shape gives bitwise the same result. */
 elmrt_status elmrt_set_tiling(elmrt_sim* s, int32_t tx, int32_t ty, int32_t tm);
 
 /* Release the handle (not the workspace).  NULL is ignored. */
