@@ -87,8 +87,9 @@ elmrt_status elmrt_workspace_bytes(const elmrt_params* p, size_t* bytes);
  * 256-byte aligned, >= elmrt_workspace_bytes) and HIP stream (hipStream_t, or
  * NULL for the null stream).  Fails with ELMRT_E_INVALID on: unknown lattice,
  * precision, collision or bc; n < 4 on an axis (nz != 1 for D2Q9); cells
- * >= 2^31; a, b, R <= 0; T/Tc outside (0, 1); kappa_tilde < 0; nu <= 0;
- * rho_liquid <= rho_vapour when the viscosities differ. */
+ * >= 2^31; Q x (cells per plane normal to the last axis) x value size
+ * >= 2^31 bytes; a, b, R <= 0; T/Tc outside (0, 1); kappa_tilde < 0;
+ * nu <= 0; rho_liquid <= rho_vapour when the viscosities differ. */
 elmrt_status elmrt_create(const elmrt_params* p, void* dev_workspace, size_t workspace_bytes,
                           void* hip_stream, elmrt_sim** out);
 

@@ -155,6 +155,13 @@ elmrt_status validate(const elmrt_params* p)
     if (D == 2 && p->n[2] != 1) return fail(ELMRT_E_INVALID, "D2Q9 needs n[2] == 1");
     const long double cells = (long double)p->n[0] * p->n[1] * p->n[2];
     if (cells >= 2147483648.0L) return fail(ELMRT_E_INVALID, "grid has >= 2^31 cells");
+    {
+        // a plane block (Q populations of one plane normal to the last axis) is
+        // addressed with 32-bit offsets
+        const long double plane = D == 3 ? (long double)p->n[0] * p->n[1] : (long double)p->n[0];
+        const long double block = plane * (D == 3 ? 27 : 9) * (p->precision == ELMRT_FP64 ? 8 : 4);
+        if (block >= 2147483648.0L) return fail(ELMRT_E_INVALID, "plane block (Q x cells per plane x value size) >= 2^31 bytes");
+    }
     if (!(p->eos_a > 0) || !(p->eos_b > 0) || !(p->eos_R > 0)) return fail(ELMRT_E_INVALID, "EOS a, b, R must be > 0");
     if (!(p->T_over_Tc > 0 && p->T_over_Tc < 1)) return fail(ELMRT_E_INVALID, "T/Tc must be in (0, 1)");
     if (!(p->kappa_tilde >= 0) || !std::isfinite(p->kappa_tilde)) return fail(ELMRT_E_INVALID, "kappa_tilde must be >= 0");

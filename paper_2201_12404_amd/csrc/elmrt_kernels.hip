@@ -2,9 +2,14 @@
 // multi-relaxation-time two-phase lattice Boltzmann model (Hosseini, Dorschner
 // & Karlin, arXiv:2201.12404).
 //
-// State layout (device, structure of arrays): cur[i*N + cell], cell = x +
-// nx*(y + ny*z).  The buffer holds post-collision populations f'(r, t-1) at the
-// cell they leave from, so the populations of time t are gathered by pulling:
+// State layout (device): planes normal to the last axis (z in 3-D, y in 2-D)
+// are stored one after another, and within a plane the Q populations are
+// stored as separate arrays: cur[(m*Q + i)*P + c], m = the plane index, P =
+// cells per plane, c = x (+ nx*y in 3-D).  A plane block (Q*P values) is the
+// unit a kernel addresses with one scalar resource; population i sits at the
+// scalar offset i*P*sizeof(T) in it.  The buffer holds post-collision
+// populations f'(r, t-1) at the cell they leave from, so the populations of
+// time t are gathered by pulling:
 //   f_i(r, t) = cur_i(r - c_i)        (periodic wrap), or
 //   f_i(r, t) = cur_{-i}(r)           (half-way bounce-back when r - c_i is
 //                                      behind a wall).
@@ -88,26 +93,42 @@ __device__ __forceinline__ int map_coord(int x, int n, int wall, int* flip)
     return r;
 }
 
-// Pull addressing of one cell: source offsets and validity per axis and
-// per velocity component c (index c + 1).
+// Cells per plane normal to the last axis.
+template <int D>
+__host__ __device__ __forceinline__ int plane_cells(const Grid& g)
+{
+    return D == 3 ? g.nxny : g.n[0];
+}
+
+// Element index of population i of cell (in-plane offset c, plane m).
+template <int D>
+__device__ __forceinline__ size_t sidx(const Grid& g, int i, int c, int m)
+{
+    constexpr int Q = Lat<D>::Q;
+    return ((size_t)m * Q + i) * (size_t)plane_cells<D>(g) + c;
+}
+
+// Pull addressing of one cell: in-plane source offsets and the source plane
+// per velocity component c (index c + 1), with their validity.
 struct PullIdx {
-    int off[3][3];
+    int off[2][3];    // in-plane axes (x; y in 3-D): element offsets
+    int pl[3];        // marching axis: source plane
     bool ok[3][3];
-    int self;
+    int cself, mself;
 };
 
 template <int D>
 __device__ __forceinline__ void pull_setup(const Grid& g, int x, int y, int z, PullIdx& P)
 {
     const int co[3] = {x, y, z};
-    const int st[3] = {1, g.n[0], g.nxny};
+    const int st[2] = {1, g.n[0]};
 #pragma unroll
     for (int a = 0; a < 3; ++a) {
 #pragma unroll
         for (int k = 0; k < 3; ++k) {
             if (a >= D) {
-                P.off[a][k] = 0;
                 P.ok[a][k] = true;
+                if (a < 2) P.off[a][k] = 0;
                 continue;
             }
             const int n = g.n[a];
@@ -119,11 +140,13 @@ __device__ __forceinline__ void pull_setup(const Grid& g, int x, int y, int z, P
                 ok = (s >= 0) && (s < n);
                 s = ok ? s : co[a];
             }
-            P.off[a][k] = s * st[a];
+            if (a == D - 1) P.pl[k] = s;
+            else P.off[a][k] = s * st[a];
             P.ok[a][k] = ok;
         }
     }
-    P.self = x + g.n[0] * y + g.nxny * z;
+    P.cself = (D == 3) ? x + g.n[0] * y : x;
+    P.mself = (D == 3) ? z : y;
 }
 
 template <int D, typename T>
@@ -135,38 +158,40 @@ __device__ __forceinline__ void pull(const T* __restrict__ cur, const Grid& g, c
     for (int i = 0; i < Q; ++i) {
         const int a = cx_<D>(i) + 1, b = cy_<D>(i) + 1, c = cz_<D>(i) + 1;
         const bool ok = P.ok[0][a] && P.ok[1][b] && P.ok[2][c];
-        const int src = P.off[0][a] + P.off[1][b] + P.off[2][c];
+        const int cm = (D == 3) ? c : b;
+        const int src = P.off[0][a] + ((D == 3) ? P.off[1][b] : 0);
         // bounce-back: the population that left r towards the wall, reversed
-        const size_t idx = ok ? (size_t)i * g.N + src : (size_t)(Q - 1 - i) * g.N + P.self;
+        const size_t idx = ok ? sidx<D>(g, i, src, P.pl[cm]) : sidx<D>(g, Q - 1 - i, P.cself, P.mself);
         f[i] = cur[idx];
     }
 }
 
 // rho = sum f, j = sum c f, accumulated in A in a fixed order (identical
-// wherever it is used).
+// wherever it is used): differences and sums along x lines, then the line
+// sums combined for rho, j_y and j_z.
 template <int D, typename T, typename A>
 __device__ __forceinline__ void moments(const T (&f)[Lat<D>::Q], A& rho, A (&j)[3])
 {
-    constexpr int Q = Lat<D>::Q;
-    A r = A(0), jx = A(0), jy = A(0), jz = A(0);
+    constexpr int NZ = (D == 3) ? 3 : 1;
+    A L[3][3], jx = A(0);
 #pragma unroll
-    for (int i = 0; i < Q; ++i) r += (A)f[i];
+    for (int z = 0; z < NZ; ++z)
 #pragma unroll
-    for (int i = 0; i < Q; ++i) {
-        if (cx_<D>(i) > 0) jx += (A)f[i];
-        if (cx_<D>(i) < 0) jx -= (A)f[i];
-    }
+        for (int y = 0; y < 3; ++y) {
+            const int b = 3 * y + 9 * z;
+            const A p = (A)f[b + 2], m = (A)f[b], o = (A)f[b + 1];
+            jx += p - m;
+            L[y][z] = (p + m) + o;
+        }
+    A r = A(0), jy = A(0), jz = A(0);
 #pragma unroll
-    for (int i = 0; i < Q; ++i) {
-        if (cy_<D>(i) > 0) jy += (A)f[i];
-        if (cy_<D>(i) < 0) jy -= (A)f[i];
+    for (int z = 0; z < NZ; ++z) {
+        r += (L[0][z] + L[1][z]) + L[2][z];
+        jy += L[2][z] - L[0][z];
     }
     if (D == 3) {
 #pragma unroll
-        for (int i = 0; i < Q; ++i) {
-            if (cz_<D>(i) > 0) jz += (A)f[i];
-            if (cz_<D>(i) < 0) jz -= (A)f[i];
-        }
+        for (int y = 0; y < 3; ++y) jz += L[y][2] - L[y][0];
     }
     rho = r;
     j[0] = jx;
@@ -258,23 +283,28 @@ __device__ __forceinline__ void conserve_mass(T (&f)[Lat<D>::Q], A rho)
 // 1000 steps, where all-FP32 arithmetic drifts by ~5e-5 (low-density
 // interface cells, where the bare velocity and F/rho are O(1) and nearly
 // cancel, are the most sensitive).
+//
+// Every product-form quantity is evaluated through its factors: f^eq and f*
+// from the x-y factor products times the z factor, the second moments of
+// f - f^eq from sums along x lines, and s (the stress part, Appendix A) as
+// e_z A(x,y) + phi2_z B(x,y) + phi1_z C(x,y), where A, B, C collect the 1-D
+// dual functions of the x and y axes.
 template <int D, typename T, typename A>
 __device__ __forceinline__ void collide(T (&f)[Lat<D>::Q], A rho, const A (&j)[3], const A (&F)[3],
                                         const A (&Phi)[3], A omega, int entropic)
 {
     constexpr int Q = Lat<D>::Q;
+    constexpr int ZL = (D == 3) ? 0 : 1, ZH = (D == 3) ? 2 : 1;   // z index range (c_z + 1)
     const A third = A(1) / A(3);
     const A inv_rho = rcp<A>(rho);
     A u[3] = {A(0), A(0), A(0)};
     A e[3][3], gs[3][3];
-    T ef[3][3];
     bool pos = rho > A(0);
 #pragma unroll
     for (int a = 0; a < 3; ++a) {
         if (a >= D) {
             e[a][0] = e[a][2] = gs[a][0] = gs[a][2] = A(0);
             e[a][1] = gs[a][1] = A(1);
-            ef[a][0] = ef[a][2] = T(0); ef[a][1] = T(1);
             continue;
         }
         u[a] = j[a] * inv_rho;
@@ -288,78 +318,126 @@ __device__ __forceinline__ void collide(T (&f)[Lat<D>::Q], A rho, const A (&j)[3
         gs[a][2] = A(0.5) * (zs + xs);
         gs[a][0] = A(0.5) * (zs - xs);
         pos = pos && gs[a][0] > A(0) && gs[a][1] > A(0) && gs[a][2] > A(0);
-#pragma unroll
-        for (int k = 0; k < 3; ++k) ef[a][k] = (T)e[a][k];
     }
-    // pass 1: f - f^eq (f^eq formed in A; the difference is small) and its second moments
-    T Pxx = T(0), Pyy = T(0), Pzz = T(0), Pxy = T(0), Pxz = T(0), Pyz = T(0);
+    // rho times the x-y factor products of f^eq and f*
+    A re[3][3], rg[3][3];
+#pragma unroll
+    for (int x = 0; x < 3; ++x)
+#pragma unroll
+        for (int y = 0; y < 3; ++y) {
+            re[x][y] = rho * e[0][x] * e[1][y];
+            rg[x][y] = rho * gs[0][x] * gs[1][y];
+        }
+    // pass 1: f - f^eq (f^eq formed in A; the difference is small)
 #pragma unroll
     for (int i = 0; i < Q; ++i) {
-        const int cx = cx_<D>(i), cy = cy_<D>(i), cz = cz_<D>(i);
-        const A feq = rho * e[0][cx + 1] * e[1][cy + 1] * e[2][cz + 1];
-        const T fn = (T)((A)f[i] - feq);
-        f[i] = fn;
-        if (cx) Pxx += fn;
-        if (cy) Pyy += fn;
-        if (cz) Pzz += fn;
-        if (cx * cy > 0) Pxy += fn;
-        if (cx * cy < 0) Pxy -= fn;
-        if (cx * cz > 0) Pxz += fn;
-        if (cx * cz < 0) Pxz -= fn;
-        if (cy * cz > 0) Pyz += fn;
-        if (cy * cz < 0) Pyz -= fn;
+        const int x = cx_<D>(i) + 1, y = cy_<D>(i) + 1, z = cz_<D>(i) + 1;
+        f[i] = (T)((A)f[i] - re[x][y] * e[2][z]);
+    }
+    // second moments of f - f^eq (its mass and momentum vanish, so raw and
+    // central moments agree), from sums and differences along x lines
+    T Pxx = T(0), Pyy = T(0), Pzz = T(0), Pxy = T(0), Pxz = T(0), Pyz = T(0);
+    {
+        T X1[3][3], L[3][3];
+#pragma unroll
+        for (int y = 0; y < 3; ++y)
+#pragma unroll
+            for (int z = ZL; z <= ZH; ++z) {
+                const int b = 3 * y + 9 * (D == 3 ? z : 0);
+                const T p = f[b + 2], m = f[b], o = f[b + 1];
+                const T x2 = p + m;
+                X1[y][z] = p - m;
+                L[y][z] = x2 + o;
+                Pxx += x2;
+            }
+#pragma unroll
+        for (int z = ZL; z <= ZH; ++z) {
+            Pxy += X1[2][z] - X1[0][z];
+            Pyy += L[2][z] + L[0][z];
+        }
+        if (D == 3) {
+#pragma unroll
+            for (int y = 0; y < 3; ++y) {
+                Pxz += X1[y][2] - X1[y][0];
+                Pzz += L[y][2] + L[y][0];
+            }
+            Pyz = (L[2][2] - L[2][0]) - (L[0][2] - L[0][0]);
+        }
     }
     const T om1 = (T)(A(1) - omega);
-    T ch = T(0);
-    if (entropic) {
+    if (!entropic) {
+        // BGK: f' = f* + (1 - omega)(f - f^eq)
+#pragma unroll
+        for (int i = 0; i < Q; ++i) {
+            const int x = cx_<D>(i) + 1, y = cy_<D>(i) + 1, z = cz_<D>(i) + 1;
+            f[i] = (T)(rg[x][y] * gs[2][z] + (A)(om1 * f[i]));
+        }
+        if constexpr (sizeof(T) < sizeof(A)) conserve_mass<D, T, A>(f, rho);
+        return;
+    }
+    // trace in h: s carries the deviatoric part only
+    {
         const T tr = (D == 3) ? (Pxx + Pyy + Pzz) * (T(1) / T(3)) : (Pxx + Pyy) * T(0.5);
         Pxx -= tr;
         Pyy -= tr;
         Pzz = (D == 3) ? Pzz - tr : T(0);
     }
-    T p1[3][3];
+    // 1-D duals: phi0 = the equilibrium factors, phi1 = {u - 1/2, -2u, u + 1/2},
+    // phi2 = {1/2, -1, 1/2}
+    T ef[3][3], p1[3][3];
 #pragma unroll
     for (int a = 0; a < 3; ++a) {
+#pragma unroll
+        for (int k = 0; k < 3; ++k) ef[a][k] = (T)e[a][k];
         p1[a][0] = (T)(u[a] - A(0.5));
         p1[a][1] = (T)(A(-2) * u[a]);
         p1[a][2] = (T)(u[a] + A(0.5));
     }
     const T p2[3] = {T(0.5), T(-1), T(0.5)};
-    auto s_of = [&](int cx, int cy, int cz) -> T {
-        const T ex = ef[0][cx + 1], ey = ef[1][cy + 1], ez = ef[2][cz + 1];
-        const T px = p1[0][cx + 1], py = p1[1][cy + 1], pz = p1[2][cz + 1];
-        T s = Pxx * p2[cx + 1] * ey * ez + Pyy * ex * p2[cy + 1] * ez + Pxy * px * py * ez;
-        if (D == 3) s += Pzz * ex * ey * p2[cz + 1] + Pxz * px * ey * pz + Pyz * ex * py * pz;
-        return s;
-    };
-    if (entropic) {
-        T ig[3][3];
+    T s[Q];
 #pragma unroll
-        for (int a = 0; a < 3; ++a)
+    for (int x = 0; x < 3; ++x)
 #pragma unroll
-            for (int k = 0; k < 3; ++k) ig[a][k] = (a >= D) ? T(1) : (T)rcp<A>(gs[a][k]);
-        const T irt = (T)inv_rho;
-        T S = T(0), H = T(0);
+        for (int y = 0; y < 3; ++y) {
+            const T ex = ef[0][x], ey = ef[1][y], px = p1[0][x], py = p1[1][y];
+            const T Axy = (Pxx * p2[x]) * ey + ex * (Pyy * p2[y]) + (Pxy * px) * py;
+            if (D == 3) {
+                const T Bxy = (Pzz * ex) * ey;
+                const T Cxy = (Pxz * px) * ey + ex * (Pyz * py);
 #pragma unroll
-        for (int i = 0; i < Q; ++i) {
-            const int cx = cx_<D>(i), cy = cy_<D>(i), cz = cz_<D>(i);
-            const T s = s_of(cx, cy, cz);
-            const T h = f[i] - s;
-            const T w = irt * ig[0][cx + 1] * ig[1][cy + 1] * ig[2][cz + 1];
-            const T hw = h * w;
-            S += s * hw;
-            H += h * hw;
+                for (int z = 0; z < 3; ++z) s[x + 3 * y + 9 * z] = Axy * ef[2][z] + Bxy * p2[z] + Cxy * p1[2][z];
+            } else {
+                s[x + 3 * y] = Axy;
+            }
         }
-        ch = (pos && (A)H > Eps2<A>::v * rho) ? (T)(omega - A(1)) * S * rcp<T>(H) : T(0);
-    }
-    // f' = f* + (1 - omega) s + (1 - omega gamma/2) h, h = (f - f^eq) - s; BGK: s = 0, h = f - f^eq
+    // entropic scalar products <s|h> and <h|h> with weights 1/f*
+    T ig[3][3];
+#pragma unroll
+    for (int a = 0; a < 3; ++a)
+#pragma unroll
+        for (int k = 0; k < 3; ++k) ig[a][k] = (a >= D) ? T(1) : rcp<T>((T)gs[a][k]);
+    const T irt = (T)inv_rho;
+    T wxy[3][3];
+#pragma unroll
+    for (int x = 0; x < 3; ++x)
+#pragma unroll
+        for (int y = 0; y < 3; ++y) wxy[x][y] = irt * ig[0][x] * ig[1][y];
+    T S = T(0), H = T(0);
 #pragma unroll
     for (int i = 0; i < Q; ++i) {
-        const int cx = cx_<D>(i), cy = cy_<D>(i), cz = cz_<D>(i);
-        const T s = entropic ? s_of(cx, cy, cz) : T(0);
-        const A fs = rho * gs[0][cx + 1] * gs[1][cy + 1] * gs[2][cz + 1];
-        const T small = entropic ? (om1 * s + ch * (f[i] - s)) : om1 * f[i];
-        f[i] = (T)(fs + (A)small);
+        const int x = cx_<D>(i) + 1, y = cy_<D>(i) + 1, z = cz_<D>(i) + 1;
+        const T h = f[i] - s[i];
+        const T hw = h * (wxy[x][y] * ig[2][z]);
+        S += s[i] * hw;
+        H += h * hw;
+        f[i] = h;
+    }
+    const T ch = (pos && (A)H > Eps2<A>::v * rho) ? (T)(omega - A(1)) * S * rcp<T>(H) : T(0);
+    // f' = f* + (1 - omega) s + (1 - omega gamma/2) h
+#pragma unroll
+    for (int i = 0; i < Q; ++i) {
+        const int x = cx_<D>(i) + 1, y = cy_<D>(i) + 1, z = cz_<D>(i) + 1;
+        f[i] = (T)(rg[x][y] * gs[2][z] + (A)(om1 * s[i] + ch * f[i]));
     }
     if constexpr (sizeof(T) < sizeof(A)) conserve_mass<D, T, A>(f, rho);
 }
@@ -387,55 +465,86 @@ __device__ __forceinline__ void flat_coords(uint32_t cell, const FlatGrid& fg, i
 // its offsets and wall tests are scalar; the in-plane offsets are computed
 // once per thread and reused for every plane.
 
-// Raw buffer resource over one plane [base, base + bytes): loads and stores
-// take a 32-bit per-lane byte offset and a scalar resource, so no 64-bit
-// address is formed per lane; an offset outside the plane reads 0 and writes
-// nothing instead of touching other memory.
-__device__ __forceinline__ __amdgpu_buffer_rsrc_t plane_rsrc(const void* base, uint32_t bytes)
+// Field planes (rho, q: plain [z][y][x] arrays): a workgroup-uniform base
+// pointer in scalar registers plus a 32-bit per-lane byte offset, so no 64-bit
+// address is formed per lane.  The base is read from the first lane, which
+// states its uniformity to the compiler.
+__device__ __forceinline__ const char* plane_ptr(const void* base)
 {
-    return __builtin_amdgcn_make_buffer_rsrc(const_cast<void*>(base), (short)0, (int)bytes, 0x00020000);
+    const uint64_t v = (uint64_t)base;
+    const uint32_t lo = (uint32_t)__builtin_amdgcn_readfirstlane((int)(uint32_t)v);
+    const uint32_t hi = (uint32_t)__builtin_amdgcn_readfirstlane((int)(uint32_t)(v >> 32));
+    return (const char*)(((uint64_t)hi << 32) | lo);
 }
 
 template <typename T>
-__device__ __forceinline__ T bld(__amdgpu_buffer_rsrc_t r, uint32_t off);
-template <>
-__device__ __forceinline__ float bld<float>(__amdgpu_buffer_rsrc_t r, uint32_t off)
+using gptr = __attribute__((address_space(1))) T*;
+
+template <typename T>
+__device__ __forceinline__ T pld(const char* base, uint32_t off)
 {
-    return __builtin_bit_cast(float, __builtin_amdgcn_raw_buffer_load_b32(r, (int)off, 0, 0));
-}
-template <>
-__device__ __forceinline__ double bld<double>(__amdgpu_buffer_rsrc_t r, uint32_t off)
-{
-    return __builtin_bit_cast(double, __builtin_amdgcn_raw_buffer_load_b64(r, (int)off, 0, 0));
+    return *(gptr<const T>)((gptr<const char>)base + off);
 }
 template <typename T>
-__device__ __forceinline__ void bst(__amdgpu_buffer_rsrc_t r, uint32_t off, T v);
-template <>
-__device__ __forceinline__ void bst<float>(__amdgpu_buffer_rsrc_t r, uint32_t off, float v)
+__device__ __forceinline__ void pst(const char* base, uint32_t off, T v)
 {
-    __builtin_amdgcn_raw_buffer_store_b32(__builtin_bit_cast(uint32_t, v), r, (int)off, 0, 0);
+    *(gptr<T>)((gptr<char>)const_cast<char*>(base) + off) = v;
+}
+
+// Population plane blocks: one raw buffer resource per block (4 scalar
+// registers), the population selected by the scalar offset i*P*sizeof(T) and
+// the cell by a 32-bit per-lane offset.  A block of Q planes is addressed
+// with one resource, so a step holds three (the source planes) instead of Q
+// 64-bit bases.
+__device__ __forceinline__ __amdgpu_buffer_rsrc_t block_rsrc(const void* base, uint32_t bytes)
+{
+    const char* b = plane_ptr(base);
+    return __builtin_amdgcn_make_buffer_rsrc(const_cast<char*>(b), (short)0, __builtin_amdgcn_readfirstlane((int)bytes),
+                                             0x00020000);
+}
+
+template <typename T>
+__device__ __forceinline__ T bld(__amdgpu_buffer_rsrc_t r, uint32_t voff, uint32_t soff);
+template <>
+__device__ __forceinline__ float bld<float>(__amdgpu_buffer_rsrc_t r, uint32_t voff, uint32_t soff)
+{
+    return __builtin_bit_cast(float, __builtin_amdgcn_raw_buffer_load_b32(r, (int)voff, (int)soff, 0));
 }
 template <>
-__device__ __forceinline__ void bst<double>(__amdgpu_buffer_rsrc_t r, uint32_t off, double v)
+__device__ __forceinline__ double bld<double>(__amdgpu_buffer_rsrc_t r, uint32_t voff, uint32_t soff)
+{
+    return __builtin_bit_cast(double, __builtin_amdgcn_raw_buffer_load_b64(r, (int)voff, (int)soff, 0));
+}
+template <typename T>
+__device__ __forceinline__ void bst(__amdgpu_buffer_rsrc_t r, uint32_t voff, uint32_t soff, T v);
+template <>
+__device__ __forceinline__ void bst<float>(__amdgpu_buffer_rsrc_t r, uint32_t voff, uint32_t soff, float v)
+{
+    __builtin_amdgcn_raw_buffer_store_b32(__builtin_bit_cast(uint32_t, v), r, (int)voff, (int)soff, 0);
+}
+template <>
+__device__ __forceinline__ void bst<double>(__amdgpu_buffer_rsrc_t r, uint32_t voff, uint32_t soff, double v)
 {
     using u2 = __attribute__((ext_vector_type(2))) uint32_t;
-    __builtin_amdgcn_raw_buffer_store_b64(__builtin_bit_cast(u2, v), r, (int)off, 0, 0);
+    __builtin_amdgcn_raw_buffer_store_b64(__builtin_bit_cast(u2, v), r, (int)voff, (int)soff, 0);
 }
 
 // In-plane pull sources of one lane, source coordinate x - c (c = -1, 0, +1),
 // as byte offsets within a plane.
 struct LanePull {
     uint32_t xo[3], yo[3];  // yo = 0 in 2-D
-    bool xok[3], yok[3];    // false where the source lies behind a wall
+    uint32_t okb;           // bit k: x source k inside the grid; bit 3 + k: y source k
+                            // (a bit mask in one vector register, not 6 lane masks)
     uint32_t ip;            // the cell itself
 };
 
-// Marching-axis sources (uniform over the workgroup), as element offsets.
+// Marching-axis sources (uniform over the workgroup).
 struct PlanePull {
-    int mo[3];
+    int mo[3];            // source plane of component c (index c + 1)
     bool mok[3];
-    int mself;
-    uint32_t bytes;       // bytes of one plane
+    int m;                // the plane itself
+    int stride;           // cells per plane
+    uint32_t bytes;       // bytes of one population plane (P * sizeof(T))
 };
 
 __device__ __forceinline__ void axis_sources(int co, int n, int wall, int stride, int (&o)[3], bool (&ok)[3])
@@ -459,13 +568,12 @@ template <int D, typename T>
 __device__ __forceinline__ void lane_setup(const Grid& g, int x, int y, LanePull& L)
 {
     int xo[3], yo[3] = {0, 0, 0};
-    axis_sources(x, g.n[0], g.wall[0], 1, xo, L.xok);
-    if (D == 3) {
-        axis_sources(y, g.n[1], g.wall[1], g.n[0], yo, L.yok);
-    } else {
+    bool xok[3], yok[3] = {true, true, true};
+    axis_sources(x, g.n[0], g.wall[0], 1, xo, xok);
+    if (D == 3) axis_sources(y, g.n[1], g.wall[1], g.n[0], yo, yok);
+    L.okb = 0;
 #pragma unroll
-        for (int k = 0; k < 3; ++k) L.yok[k] = true;
-    }
+    for (int k = 0; k < 3; ++k) L.okb |= (xok[k] ? 1u << k : 0u) | (yok[k] ? 8u << k : 0u);
 #pragma unroll
     for (int k = 0; k < 3; ++k) {
         L.xo[k] = (uint32_t)xo[k] * (uint32_t)sizeof(T);
@@ -478,32 +586,63 @@ template <int D, typename T>
 __device__ __forceinline__ void plane_setup(const Grid& g, int m, PlanePull& P)
 {
     const int MA = D - 1;
-    const int stride = (D == 3) ? g.nxny : g.n[0];
-    axis_sources(m, g.n[MA], g.wall[MA], stride, P.mo, P.mok);
-    P.mself = m * stride;
-    P.bytes = (uint32_t)stride * (uint32_t)sizeof(T);
+    P.stride = plane_cells<D>(g);
+    axis_sources(m, g.n[MA], g.wall[MA], 1, P.mo, P.mok);
+    P.m = m;
+    P.bytes = (uint32_t)P.stride * (uint32_t)sizeof(T);
+}
+
+// Resource over the plane block of plane m.
+template <int D, typename T>
+__device__ __forceinline__ __amdgpu_buffer_rsrc_t block_of(const T* base, const PlanePull& P, int m)
+{
+    constexpr int Q = Lat<D>::Q;
+    return block_rsrc(base + (size_t)m * Q * P.stride, (uint32_t)Q * P.bytes);
+}
+
+// The byte size of a population plane, passed through an empty asm statement
+// once per plane so that the compiler forms the Q scalar offsets i * bytes
+// next to their loads instead of hoisting all of them out of the plane loop.
+__device__ __forceinline__ uint32_t opaque(uint32_t v)
+{
+    asm volatile("" : "+s"(v));
+    return v;
+}
+// The same for a per-lane value, so that conditions derived from it are
+// formed where they are used rather than held as lane masks across the loop.
+__device__ __forceinline__ uint32_t opaque_v(uint32_t v)
+{
+    asm volatile("" : "+v"(v));
+    return v;
 }
 
 // Gather f_i(r, t) of one cell.  FAST: no source of this workgroup and plane
 // lies behind a wall (no bounce-back selects needed).
 template <int D, typename T, bool FAST>
-__device__ __forceinline__ void pull_m(const T* __restrict__ cur, int N, const LanePull& L, const PlanePull& P,
+__device__ __forceinline__ void pull_m(const T* __restrict__ cur, const LanePull& L, const PlanePull& P,
                                        T (&f)[Lat<D>::Q])
 {
     constexpr int Q = Lat<D>::Q;
+    const uint32_t pb = opaque(P.bytes);
+    const uint32_t okb = FAST ? 0u : opaque_v(L.okb);
+    __amdgpu_buffer_rsrc_t R[3];
+#pragma unroll
+    for (int k = 0; k < 3; ++k) R[k] = block_of<D, T>(cur, P, P.mo[k]);
 #pragma unroll
     for (int i = 0; i < Q; ++i) {
         const int cx = cx_<D>(i) + 1, cy = cy_<D>(i) + 1, cz = cz_<D>(i) + 1;
         const int cm = (D == 3) ? cz : cy;           // component along the marching axis
         const uint32_t off = L.xo[cx] + ((D == 3) ? L.yo[cy] : 0u);
-        const auto r = plane_rsrc(cur + (size_t)i * N + P.mo[cm], P.bytes);
         if (FAST) {
-            f[i] = bld<T>(r, off);
+            f[i] = bld<T>(R[cm], off, (uint32_t)i * pb);
         } else {
-            const bool ok = L.xok[cx] && ((D == 3) ? L.yok[cy] : true) && P.mok[cm];
-            // bounce-back: the population that left r towards the wall, reversed
-            const auto rb = plane_rsrc(cur + (size_t)(Q - 1 - i) * N + P.mself, P.bytes);
-            f[i] = ok ? bld<T>(r, off) : bld<T>(rb, L.ip);
+            const bool ok = ((okb >> cx) & (okb >> (3 + cy)) & 1u) && P.mok[cm];
+            // bounce-back: the population that left r towards the wall, reversed.
+            // Both loads are issued (each source is inside the grid), so that the
+            // per-lane choice selects a value and never a resource.
+            const T fs = bld<T>(R[cm], off, (uint32_t)i * pb);
+            const T fb = bld<T>(R[1], L.ip, (uint32_t)(Q - 1 - i) * pb);
+            f[i] = ok ? fs : fb;
         }
     }
 }
@@ -561,16 +700,17 @@ __global__ __launch_bounds__(TX* TY) void k_macro(const T* __restrict__ cur, T* 
         PlanePull P;
         plane_setup<D, T>(g, m, P);
         T f[Q];
-        if (clear && P.mok[0] && P.mok[2]) pull_m<D, T, true>(cur, g.N, L, P, f);
-        else pull_m<D, T, false>(cur, g.N, L, P, f);
+        if (clear && P.mok[0] && P.mok[2]) pull_m<D, T, true>(cur, L, P, f);
+        else pull_m<D, T, false>(cur, L, P, f);
         double rho, j[3];
         moments<D, T, double>(f, rho, j);
-        bst<T>(plane_rsrc(rho_out + P.mself, P.bytes), L.ip, (T)rho);
+        const size_t mself = (size_t)P.m * P.stride;
+        pst<T>(plane_ptr(rho_out + mself), L.ip, (T)rho);
         const double inv = rcp<double>(rho);
 #pragma unroll
         for (int a = 0; a < D; ++a) {
             const double ua = j[a] * inv;
-            bst<T>(plane_rsrc(q_out + (size_t)a * g.N + P.mself, P.bytes), L.ip, (T)(j[a] * ua * ua));
+            pst<T>(plane_ptr(q_out + (size_t)a * g.N + mself), L.ip, (T)(j[a] * ua * ua));
         }
         bad = bad || !(rho > 0.0) || !isfinite(rho);
     }
@@ -589,7 +729,7 @@ __global__ __launch_bounds__(TX* TY) void k_collide(const T* __restrict__ cur, T
     constexpr int NT = TX * TY;
     constexpr int NE = (HX * HY + NT - 1) / NT;   // halo entries staged per thread and plane
     constexpr int MA = D - 1;
-    __shared__ V2<T> tile[5][HY][HX];
+    __shared__ V2<double> tile[5][HY][HX];   // rho and signed psi, FP64
 
     const TileCoords t = tile_of<D, TX, TY>(g, bx, by, tm);
     const int tx = threadIdx.x;
@@ -616,16 +756,15 @@ __global__ __launch_bounds__(TX* TY) void k_collide(const T* __restrict__ cur, T
     }
     auto load_plane = [&](int slot, int m) {
         int dummy = 0;
-        const auto rp = plane_rsrc(rho + (size_t)map_coord(m, g.n[MA], g.wall[MA], &dummy) * mstride,
-                                   (uint32_t)mstride * (uint32_t)sizeof(T));
+        const char* rp = plane_ptr(rho + (size_t)map_coord(m, g.n[MA], g.wall[MA], &dummy) * mstride);
 #pragma unroll
         for (int k = 0; k < NE; ++k) {
             if (hoff[k] >= 0) {
                 const int e = lid + k * NT;
-                const T r = bld<T>(rp, (uint32_t)hoff[k]);
-                V2<T> v;
+                const double r = (double)pld<T>(rp, (uint32_t)hoff[k]);
+                V2<double> v;
                 v.rho = r;
-                v.psi = (T)psi_signed<double>((double)r, ph);
+                v.psi = psi_signed<double>(r, ph);
                 (&tile[slot][0][0])[e] = v;
             }
         }
@@ -644,8 +783,8 @@ __global__ __launch_bounds__(TX* TY) void k_collide(const T* __restrict__ cur, T
         plane_setup<D, T>(g, m, P);
         T f[Q];
         if (active) {
-            if (clear && P.mok[0] && P.mok[2]) pull_m<D, T, true>(cur, g.N, L, P, f);
-            else pull_m<D, T, false>(cur, g.N, L, P, f);
+            if (clear && P.mok[0] && P.mok[2]) pull_m<D, T, true>(cur, L, P, f);
+            else pull_m<D, T, false>(cur, L, P, f);
         }
         load_plane((m - t.m0 + 4) % 5, m + 2);
         __syncthreads();
@@ -654,38 +793,45 @@ __global__ __launch_bounds__(TX* TY) void k_collide(const T* __restrict__ cur, T
 #pragma unroll
             for (int d = 0; d < 5; ++d) sl[d] = (m - t.m0 + d) % 5;   // plane m + d - 2
             const int hy0 = (D == 3) ? ty + 2 : 0;
-            const V2<T> c0 = tile[sl[2]][hy0][tx + 2];
+            const V2<double> c0 = tile[sl[2]][hy0][tx + 2];
             // force stencils (Sec. 2.3): sums of 3 w_i c_i times
-            // [4/3 psi(r+c_i) - 1/6 psi(r+2c_i)] and [rho(r+2c_i) - 2 rho(r+c_i)]
+            // [4/3 psi(r+c_i) - 1/6 psi(r+2c_i)] and [rho(r+2c_i) - 2 rho(r+c_i)],
+            // taken over the pairs (c, -c) so that each pair costs one
+            // difference per radius; 3 w_i = 3 (1/6)^k (2/3)^(D-k) for k
+            // nonzero components.  FP64 throughout: at an interface the terms
+            // are O(1) and the force is divided by the vapour density.
             double G[3] = {0.0, 0.0, 0.0}, K[3] = {0.0, 0.0, 0.0};
 #pragma unroll
-            for (int i = 0; i < Q; ++i) {
+            for (int i = (Q + 1) / 2; i < Q; ++i) {
                 const int cx = cx_<D>(i), cy = cy_<D>(i), cz = cz_<D>(i);
-                if (cx == 0 && cy == 0 && cz == 0) continue;
-                // 3 w_i: product of one-dimensional weights 2/3 (c=0), 1/6 (c=+-1)
-                double w3 = 3.0;
-                w3 *= (cx ? 1.0 / 6.0 : 2.0 / 3.0);
-                w3 *= (cy ? 1.0 / 6.0 : 2.0 / 3.0);
-                if (D == 3) w3 *= (cz ? 1.0 / 6.0 : 2.0 / 3.0);
-                V2<T> v1, v2;
+                const int k = (cx != 0) + (cy != 0) + (cz != 0);
+                const double w = (k == 1) ? ((D == 3) ? 2.0 / 9.0 : 1.0 / 3.0)
+                                          : (k == 2) ? ((D == 3) ? 1.0 / 18.0 : 1.0 / 12.0) : 1.0 / 72.0;
+                V2<double> p1, p2, m1, m2;
                 if (D == 3) {
-                    v1 = tile[sl[2 + cz]][hy0 + cy][tx + 2 + cx];
-                    v2 = tile[sl[2 + 2 * cz]][hy0 + 2 * cy][tx + 2 + 2 * cx];
+                    p1 = tile[sl[2 + cz]][hy0 + cy][tx + 2 + cx];
+                    p2 = tile[sl[2 + 2 * cz]][hy0 + 2 * cy][tx + 2 + 2 * cx];
+                    m1 = tile[sl[2 - cz]][hy0 - cy][tx + 2 - cx];
+                    m2 = tile[sl[2 - 2 * cz]][hy0 - 2 * cy][tx + 2 - 2 * cx];
                 } else {
-                    v1 = tile[sl[2 + cy]][0][tx + 2 + cx];
-                    v2 = tile[sl[2 + 2 * cy]][0][tx + 2 + 2 * cx];
+                    p1 = tile[sl[2 + cy]][0][tx + 2 + cx];
+                    p2 = tile[sl[2 + 2 * cy]][0][tx + 2 + 2 * cx];
+                    m1 = tile[sl[2 - cy]][0][tx + 2 - cx];
+                    m2 = tile[sl[2 - 2 * cy]][0][tx + 2 - 2 * cx];
                 }
-                const double tt = w3 * (4.0 / 3.0 * fabs((double)v1.psi) - 1.0 / 6.0 * fabs((double)v2.psi));
-                const double kk = w3 * ((double)v2.rho - 2.0 * (double)v1.rho);
-                if (cx > 0) { G[0] += tt; K[0] += kk; }
-                if (cx < 0) { G[0] -= tt; K[0] -= kk; }
-                if (cy > 0) { G[1] += tt; K[1] += kk; }
-                if (cy < 0) { G[1] -= tt; K[1] -= kk; }
-                if (cz > 0) { G[2] += tt; K[2] += kk; }
-                if (cz < 0) { G[2] -= tt; K[2] -= kk; }
-                // evaluate the stencil in groups of directions so that only one
-                // group of LDS values (widened to FP64) is live at a time
-                if (i % 9 == 8) __builtin_amdgcn_sched_barrier(0);
+                const double tt = (w * (4.0 / 3.0)) * (fabs(p1.psi) - fabs(m1.psi)) - (w * (1.0 / 6.0)) * (fabs(p2.psi) - fabs(m2.psi));
+                const double kk = w * (p2.rho - m2.rho) - (2.0 * w) * (p1.rho - m1.rho);
+                const int c[3] = {cx, cy, cz};
+#pragma unroll
+                for (int a = 0; a < 3; ++a) {
+                    if (c[a] > 0) { G[a] += tt; K[a] += kk; }
+                    if (c[a] < 0) { G[a] -= tt; K[a] -= kk; }
+                }
+                // a few pairs at a time, so that only their LDS values are live:
+                // the sums so far are pinned here and later LDS loads may not
+                // move above this point
+                if ((i - (Q + 1) / 2) % 4 == 3)
+                    asm volatile("" : "+v"(G[0]), "+v"(G[1]), "+v"(G[2]), "+v"(K[0]), "+v"(K[1]), "+v"(K[2])::"memory");
             }
             double rhoc, j[3];
             moments<D, T, double>(f, rhoc, j);
@@ -698,24 +844,32 @@ __global__ __launch_bounds__(TX* TY) void k_collide(const T* __restrict__ cur, T
                 // q_a at r + e_a (source of c_a = -1, index 0) and r - e_a (index 2);
                 // behind a wall the mirrored value is the cell itself, negated
                 const T* qa = q + (size_t)a * g.N;
-                const auto qm0 = plane_rsrc(qa + P.mself, P.bytes);
-                const T qself = bld<T>(qm0, L.ip);
+                const char* qm0 = plane_ptr(qa + (size_t)P.m * P.stride);
+                const T qself = pld<T>(qm0, L.ip);
                 T qp, qm;
                 if (a == MA) {
-                    qp = P.mok[0] ? bld<T>(plane_rsrc(qa + P.mo[0], P.bytes), L.ip) : -qself;
-                    qm = P.mok[2] ? bld<T>(plane_rsrc(qa + P.mo[2], P.bytes), L.ip) : -qself;
+                    qp = P.mok[0] ? pld<T>(plane_ptr(qa + (size_t)P.mo[0] * P.stride), L.ip) : -qself;
+                    qm = P.mok[2] ? pld<T>(plane_ptr(qa + (size_t)P.mo[2] * P.stride), L.ip) : -qself;
                 } else if (a == 0) {
-                    qp = L.xok[0] ? bld<T>(qm0, L.xo[0] + L.yo[1]) : -qself;
-                    qm = L.xok[2] ? bld<T>(qm0, L.xo[2] + L.yo[1]) : -qself;
+                    const T vp = pld<T>(qm0, L.xo[0] + L.yo[1]), vm = pld<T>(qm0, L.xo[2] + L.yo[1]);
+                    const uint32_t okb = opaque_v(L.okb);
+                    qp = (okb & 1u) ? vp : -qself;
+                    qm = (okb & 4u) ? vm : -qself;
                 } else {
-                    qp = L.yok[0] ? bld<T>(qm0, L.xo[1] + L.yo[0]) : -qself;
-                    qm = L.yok[2] ? bld<T>(qm0, L.xo[1] + L.yo[2]) : -qself;
+                    const T vp = pld<T>(qm0, L.xo[1] + L.yo[0]), vm = pld<T>(qm0, L.xo[1] + L.yo[2]);
+                    const uint32_t okb = opaque_v(L.okb);
+                    qp = (okb & 8u) ? vp : -qself;
+                    qm = (okb & 32u) ? vm : -qself;
                 }
                 Phi[a] = half_rate * ((double)qp - (double)qm);
             }
             collide<D, T, double>(f, rhoc, j, F, Phi, omega, ph.entropic);
+            {
+                const uint32_t pb = opaque(P.bytes);
+                const auto R = block_of<D, T>(nxt, P, P.m);
 #pragma unroll
-            for (int i = 0; i < Q; ++i) bst<T>(plane_rsrc(nxt + (size_t)i * g.N + P.mself, P.bytes), L.ip, f[i]);
+                for (int i = 0; i < Q; ++i) bst<T>(R, L.ip, (uint32_t)i * pb, f[i]);
+            }
         }
         __syncthreads();
     }
@@ -812,7 +966,7 @@ __global__ __launch_bounds__(256) void k_init(const double* __restrict__ rho0, c
             const T zeta = third + ua * ua;
             v *= (dir[a] == 0) ? (T(1) - zeta) : T(0.5) * (zeta + (dir[a] > 0 ? ua : -ua));
         }
-        cur[(size_t)i * g.N + cell] = v;
+        cur[sidx<D>(g, i, (D == 3) ? co[0] + g.n[0] * co[1] : co[0], (D == 3) ? co[2] : co[1])] = v;
     }
 }
 
