@@ -125,6 +125,7 @@ def main():
     params = E.params_for(w)
     rho0, u0 = W.initial_fields(w)
     sim = E.Simulation(params)
+    tx, ty, tm = 64, 4, 16   # the library's default tiling for D3Q27
     if args.tile:
         tx, ty, tm = (int(v) for v in args.tile.split(","))
         sim.set_tiling(tx, ty, tm)
@@ -170,7 +171,7 @@ def main():
         "hbm_gbs_algorithmic_step": round(N * (b_macro + b_collide) / wall * args.steps / 1e9, 1),
         "kernels_ms": {"moments": round(avg_macro_s * 1e3, 4), "collide": round(avg_collide_s * 1e3, 4)},
         "roofline": {
-            "kernel": "k_collide<3,float,64,4>",
+            "kernel": f"k_collide<3,float,{tx},{ty}>",
             "bound": "hbm",
             "achieved": round(achieved, 1),
             "peak": HBM_PEAK_GBS,
