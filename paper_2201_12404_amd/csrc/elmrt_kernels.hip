@@ -1124,27 +1124,31 @@ bool collide_shape_supported(int D, int tx, int ty)
     return (tx == 64 && ty == 4) || (tx == 64 && ty == 2) || (tx == 32 && ty == 8) || (tx == 128 && ty == 2);
 }
 
-hipError_t launch_macro(const Launch& L, const void* cur, void* rho, void* q, unsigned* flag)
+template <int D, typename T, int TX, int TY>
+hipError_t macro_t(const Launch& L, int tm, const void* cur, void* rho, void* q, unsigned* flag)
 {
-    constexpr int TX = 64, TY = 4, TM = 8;
     const Grid& g = L.g;
     const int bx = (g.n[0] + TX - 1) / TX;
-    const int by = (L.D == 3) ? (g.n[1] + TY - 1) / TY : 1;
-    const int bm = (g.n[L.D - 1] + TM - 1) / TM;
-    const unsigned blocks = (unsigned)((long long)bx * by * bm);
-    if (L.D == 2 && !L.fp64)
-        hipLaunchKernelGGL((k_macro<2, float, 256, 1>), dim3((unsigned)((long long)((g.n[0] + 255) / 256) * bm)), dim3(256, 1), 0, L.stream,
-                           (const float*)cur, (float*)rho, (float*)q, flag, g, (g.n[0] + 255) / 256, 1, TM);
-    else if (L.D == 2)
-        hipLaunchKernelGGL((k_macro<2, double, 256, 1>), dim3((unsigned)((long long)((g.n[0] + 255) / 256) * bm)), dim3(256, 1), 0, L.stream,
-                           (const double*)cur, (double*)rho, (double*)q, flag, g, (g.n[0] + 255) / 256, 1, TM);
-    else if (!L.fp64)
-        hipLaunchKernelGGL((k_macro<3, float, TX, TY>), dim3(blocks), dim3(TX, TY), 0, L.stream,
-                           (const float*)cur, (float*)rho, (float*)q, flag, g, bx, by, TM);
-    else
-        hipLaunchKernelGGL((k_macro<3, double, TX, TY>), dim3(blocks), dim3(TX, TY), 0, L.stream,
-                           (const double*)cur, (double*)rho, (double*)q, flag, g, bx, by, TM);
+    const int by = (D == 3) ? (g.n[1] + TY - 1) / TY : 1;
+    const int bm = (g.n[D - 1] + tm - 1) / tm;
+    const long long blocks = (long long)bx * by * bm;
+    if (blocks <= 0 || blocks > 0x7fffffffLL) return hipErrorInvalidConfiguration;
+    hipLaunchKernelGGL((k_macro<D, T, TX, TY>), dim3((unsigned)blocks), dim3(TX, TY), 0, L.stream, (const T*)cur,
+                       (T*)rho, (T*)q, flag, g, bx, by, tm);
     return hipGetLastError();
+}
+
+// The moment pass takes whole rows of up to 256 cells per workgroup: the
+// x-shifted pulls of a row then touch only the row's own cache lines (the
+// periodic wrap stays in the row), where 64-cell segments share a line with
+// the neighbouring segment at each end.
+hipError_t launch_macro(const Launch& L, const void* cur, void* rho, void* q, unsigned* flag)
+{
+    constexpr int TM = 8;
+    if (L.D == 2 && !L.fp64) return macro_t<2, float, 256, 1>(L, TM, cur, rho, q, flag);
+    if (L.D == 2) return macro_t<2, double, 256, 1>(L, TM, cur, rho, q, flag);
+    if (!L.fp64) return macro_t<3, float, 256, 1>(L, TM, cur, rho, q, flag);
+    return macro_t<3, double, 256, 1>(L, TM, cur, rho, q, flag);
 }
 
 hipError_t launch_collide(const Launch& L, int tx, int ty, int tm, const void* cur, void* nxt,
