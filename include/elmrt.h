@@ -134,6 +134,55 @@ elmrt_status elmrt_coexistence(const elmrt_params* p, double* rho_vapour, double
  * tiling unchanged.  Every shape gives bitwise the same result. */
 elmrt_status elmrt_set_tiling(elmrt_sim* s, int32_t tx, int32_t ty, int32_t tm);
 
+/* Pick the collision tiling of s by measurement: every compiled tile shape
+ * of the lattice with marching depths 4..64 is run for 1 + trial_steps steps
+ * (the extra step untimed) and timed with HIP events on the sim's stream;
+ * the fastest is kept.  The trial steps advance the simulation (results do
+ * not depend on the tiling); their number is written to *steps_taken (may be
+ * NULL).  Synchronises the stream.  trial_steps >= 1. */
+elmrt_status elmrt_autotune(elmrt_sim* s, int32_t trial_steps, int64_t* steps_taken);
+
+/* ---- Batches: many independent simulations advanced together ------------
+ *
+ * A batch advances several initialised simulations of the same lattice,
+ * precision and stream with one moment launch and one collision launch per
+ * tile shape per step, whose workgroups cover the tiles of every member
+ * (a device job table maps each workgroup to its simulation and tile).  Pairs
+ * of steps are captured once into a HIP graph and replayed.  Each member
+ * evolves exactly as if stepped alone with the same tiling (bitwise), and
+ * keeps working through its own handle: elmrt_read_macros etc. see the
+ * batch's steps, and stepping a member alone between batch steps is allowed
+ * (the table is rebuilt).  The job table lives in a caller-owned device
+ * workspace of elmrt_batch_workspace_bytes(count) bytes (256-byte aligned),
+ * which must outlive the batch; the members must outlive it too. */
+typedef struct elmrt_batch elmrt_batch;
+
+elmrt_status elmrt_batch_workspace_bytes(int32_t count, size_t* bytes);
+
+/* Fails with ELMRT_E_INVALID for count < 1, a NULL or repeated member,
+ * members of different lattice, precision or stream, or a small or
+ * misaligned workspace; ELMRT_E_STATE if a member is not initialised.
+ * Uploads the job table (synchronises the stream). */
+elmrt_status elmrt_batch_create(elmrt_sim* const* sims, int32_t count, void* dev_workspace,
+                                size_t workspace_bytes, elmrt_batch** out);
+
+/* Advance every member by nsteps (asynchronous on the members' stream; the
+ * graph is captured on a private stream at first use). */
+elmrt_status elmrt_batch_step(elmrt_batch* b, int64_t nsteps);
+
+/* use_graph = 0: enqueue the launches directly instead of replaying the
+ * captured graph (same results). */
+elmrt_status elmrt_batch_set_graph(elmrt_batch* b, int32_t use_graph);
+
+/* Pick one collision tiling for all members by measurement (as
+ * elmrt_autotune, over the batch: each candidate runs 2 + trial_steps batch
+ * steps, the marching depth capped at each member's last extent).  The
+ * trial steps advance every member; their number goes to *steps_taken. */
+elmrt_status elmrt_batch_autotune(elmrt_batch* b, int32_t trial_steps, int64_t* steps_taken);
+
+/* Release the batch (not the members or the workspace).  NULL is ignored. */
+void elmrt_batch_destroy(elmrt_batch* b);
+
 /* Release the handle (not the workspace).  NULL is ignored. */
 void elmrt_destroy(elmrt_sim* s);
 

@@ -7,6 +7,8 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <array>
+#include <cstdint>
 #include <cmath>
 #include <cstdio>
 #include <cstring>
@@ -462,6 +464,366 @@ elmrt_status elmrt_set_tiling(elmrt_sim* s, int32_t tx, int32_t ty, int32_t tm)
     s->tm = tm;
     return ELMRT_OK;
 }
+
+}  // extern "C"
+
+// ------------------------------------------------------------- autotuning
+
+namespace {
+
+// Candidate collision tilings of a lattice: every compiled shape with marching
+// depths 4 .. 64.
+std::vector<std::array<int, 3>> tiling_candidates(int D)
+{
+    std::vector<std::array<int, 3>> c;
+    const int shapes2[][2] = {{64, 1}, {128, 1}, {256, 1}};
+    const int shapes3[][2] = {{64, 4}, {32, 8}, {64, 2}, {128, 2}};
+    const int tms[] = {4, 8, 16, 32, 64};
+    if (D == 2)
+        for (auto& sh : shapes2)
+            for (int tm : tms) c.push_back({sh[0], sh[1], tm});
+    else
+        for (auto& sh : shapes3)
+            for (int tm : tms) c.push_back({sh[0], sh[1], tm});
+    return c;
+}
+
+// Time 'steps' steps of fn on the stream with HIP events (milliseconds).
+template <typename F>
+elmrt_status time_steps(hipStream_t stream, F&& fn, float* ms)
+{
+    hipEvent_t a, b;
+    hipError_t e;
+    if ((e = hipEventCreate(&a)) != hipSuccess) return hip_fail(e, "hipEventCreate");
+    if ((e = hipEventCreate(&b)) != hipSuccess) {
+        (void)hipEventDestroy(a);
+        return hip_fail(e, "hipEventCreate");
+    }
+    elmrt_status st = ELMRT_OK;
+    if ((e = hipEventRecord(a, stream)) != hipSuccess) st = hip_fail(e, "hipEventRecord");
+    if (st == ELMRT_OK) st = fn();
+    if (st == ELMRT_OK && (e = hipEventRecord(b, stream)) != hipSuccess) st = hip_fail(e, "hipEventRecord");
+    if (st == ELMRT_OK && (e = hipEventSynchronize(b)) != hipSuccess) st = hip_fail(e, "hipEventSynchronize");
+    if (st == ELMRT_OK && (e = hipEventElapsedTime(ms, a, b)) != hipSuccess) st = hip_fail(e, "hipEventElapsedTime");
+    (void)hipEventDestroy(a);
+    (void)hipEventDestroy(b);
+    return st;
+}
+
+}  // namespace
+
+extern "C" {
+
+elmrt_status elmrt_autotune(elmrt_sim* s, int32_t trial_steps, int64_t* steps_taken)
+{
+    if (!s) return fail(ELMRT_E_INVALID, "sim is NULL");
+    if (trial_steps < 1) return fail(ELMRT_E_INVALID, "trial_steps must be >= 1");
+    if (!s->initialised) return fail(ELMRT_E_STATE, "elmrt_init_fields has not been called");
+    int64_t taken = 0;
+    float best = 0.f;
+    std::array<int, 3> arg{s->tx, s->ty, s->tm};
+    for (const auto& c : tiling_candidates(s->D)) {
+        s->tx = c[0];
+        s->ty = c[1];
+        s->tm = c[2];
+        float ms = 0.f;
+        elmrt_status st = step_impl(s, 1, nullptr);   // first launch of a shape: not timed
+        if (st == ELMRT_OK) st = time_steps(s->stream, [&] { return step_impl(s, trial_steps, nullptr); }, &ms);
+        if (st != ELMRT_OK) return st;
+        taken += 1 + trial_steps;
+        if (best == 0.f || ms < best) {
+            best = ms;
+            arg = c;
+        }
+    }
+    s->tx = arg[0];
+    s->ty = arg[1];
+    s->tm = arg[2];
+    if (steps_taken) *steps_taken = taken;
+    return ELMRT_OK;
+}
+
+// ---------------------------------------------------------------- batches
+
+}  // extern "C"
+
+struct elmrt_batch {
+    std::vector<elmrt_sim*> sims;
+    int D = 0, fp64 = 0;
+    hipStream_t stream = nullptr;
+    elmrt::BatchJob* djobs = nullptr;   // device table (caller's workspace)
+    std::vector<elmrt::BatchJob> hjobs;
+    std::vector<int> order;             // sims[order[k]] is table entry k
+    struct Group {
+        int tx, ty, first, count;
+        long long blocks;
+    };
+    std::vector<Group> groups;          // collision launches, one per tile shape
+    long long mblocks = 0;
+    int parity = 0;                     // steps since the table was built, mod 2
+    bool use_graph = true;
+    hipGraphExec_t exec = nullptr;      // two steps (parity 0 then 1)
+    hipGraph_t graph = nullptr;
+    hipStream_t capture = nullptr;      // private stream the graph is captured on
+                                        // (the caller's may be the null stream)
+
+    ~elmrt_batch()
+    {
+        drop_graph();
+        if (capture) (void)hipStreamDestroy(capture);
+    }
+    void drop_graph()
+    {
+        if (exec) (void)hipGraphExecDestroy(exec);
+        if (graph) (void)hipGraphDestroy(graph);
+        exec = nullptr;
+        graph = nullptr;
+    }
+};
+
+namespace {
+
+size_t batch_table_bytes(int count) { return align_up((size_t)count * sizeof(elmrt::BatchJob)); }
+
+// (Re)build the device job table from the sims' current state and tilings.
+elmrt_status batch_build(elmrt_batch* b)
+{
+    const int n = (int)b->sims.size();
+    b->order.resize(n);
+    for (int k = 0; k < n; ++k) b->order[k] = k;
+    std::stable_sort(b->order.begin(), b->order.end(), [&](int i, int j) {
+        const elmrt_sim* a = b->sims[i];
+        const elmrt_sim* c = b->sims[j];
+        return a->tx != c->tx ? a->tx < c->tx : a->ty < c->ty;
+    });
+    b->hjobs.assign(n, elmrt::BatchJob{});
+    b->groups.clear();
+    long long mfirst = 0, cfirst = 0;
+    for (int k = 0; k < n; ++k) {
+        const elmrt_sim* s = b->sims[b->order[k]];
+        if (b->groups.empty() || b->groups.back().tx != s->tx || b->groups.back().ty != s->ty) {
+            b->groups.push_back({s->tx, s->ty, k, 0, 0});
+            cfirst = 0;
+        }
+        elmrt::BatchJob& J = b->hjobs[k];
+        J.buf[0] = s->buf[0];
+        J.buf[1] = s->buf[1];
+        J.rho = s->rho;
+        J.q = s->q;
+        J.flag = s->flag;
+        J.g = s->L.g;
+        J.ph = s->ph;
+        const elmrt::Tiling mt = elmrt::macro_tiling(s->D, s->L.g);
+        const elmrt::Tiling ct = elmrt::collide_tiling(s->D, s->L.g, s->tx, s->ty, s->tm);
+        J.mbx = mt.bx;
+        J.mby = mt.by;
+        J.mtm = elmrt::kMacroTM;
+        J.cbx = ct.bx;
+        J.cby = ct.by;
+        J.ctm = s->tm;
+        J.mfirst = (int)mfirst;
+        J.cfirst = (int)cfirst;
+        J.cur0 = s->cur;
+        mfirst += mt.blocks;
+        cfirst += ct.blocks;
+        b->groups.back().count += 1;
+        b->groups.back().blocks = cfirst;
+        if (mfirst > 0x7fffffffLL || cfirst > 0x7fffffffLL) return fail(ELMRT_E_INVALID, "batch has >= 2^31 tiles");
+    }
+    b->mblocks = mfirst;
+    b->parity = 0;
+    b->drop_graph();
+    hipError_t e = hipMemcpyAsync(b->djobs, b->hjobs.data(), (size_t)n * sizeof(elmrt::BatchJob),
+                                  hipMemcpyHostToDevice, b->stream);
+    if (e == hipSuccess) e = hipStreamSynchronize(b->stream);
+    if (e != hipSuccess) return hip_fail(e, "job table upload");
+    return ELMRT_OK;
+}
+
+// One batched step at the given parity: the moment pass over every job, then
+// one collision launch per tile shape.
+elmrt_status batch_enqueue_step(elmrt_batch* b, int parity, hipStream_t stream)
+{
+    hipError_t e = elmrt::launch_macro_batch(b->D, b->fp64, b->djobs, (int)b->hjobs.size(), b->mblocks, parity,
+                                             stream);
+    if (e != hipSuccess) return hip_fail(e, "batched moment kernel");
+    for (const auto& G : b->groups) {
+        e = elmrt::launch_collide_batch(b->D, b->fp64, G.tx, G.ty, b->djobs + G.first, G.count, G.blocks, parity,
+                                        stream);
+        if (e != hipSuccess) return hip_fail(e, "batched collision kernel");
+    }
+    return ELMRT_OK;
+}
+
+// The sims' buffer indices still match the table (nobody stepped them alone).
+bool batch_in_sync(const elmrt_batch* b)
+{
+    for (size_t k = 0; k < b->hjobs.size(); ++k)
+        if (b->sims[b->order[k]]->cur != (b->hjobs[k].cur0 ^ b->parity)) return false;
+    return true;
+}
+
+elmrt_status batch_capture(elmrt_batch* b)
+{
+    hipError_t e;
+    if (!b->capture && (e = hipStreamCreateWithFlags(&b->capture, hipStreamNonBlocking)) != hipSuccess)
+        return hip_fail(e, "hipStreamCreateWithFlags");
+    e = hipStreamBeginCapture(b->capture, hipStreamCaptureModeThreadLocal);
+    if (e != hipSuccess) return hip_fail(e, "hipStreamBeginCapture");
+    elmrt_status st = batch_enqueue_step(b, 0, b->capture);
+    if (st == ELMRT_OK) st = batch_enqueue_step(b, 1, b->capture);
+    hipGraph_t g = nullptr;
+    e = hipStreamEndCapture(b->capture, &g);
+    if (st != ELMRT_OK) {
+        if (g) (void)hipGraphDestroy(g);
+        return st;
+    }
+    if (e != hipSuccess) return hip_fail(e, "hipStreamEndCapture");
+    b->graph = g;
+    e = hipGraphInstantiate(&b->exec, g, nullptr, nullptr, 0);
+    if (e != hipSuccess) {
+        b->drop_graph();
+        return hip_fail(e, "hipGraphInstantiate");
+    }
+    return ELMRT_OK;
+}
+
+elmrt_status batch_step_impl(elmrt_batch* b, int64_t nsteps)
+{
+    if (!batch_in_sync(b)) {
+        elmrt_status st = batch_build(b);
+        if (st != ELMRT_OK) return st;
+    }
+    int64_t k = 0;
+    auto advance = [&](int64_t n) {
+        b->parity ^= (int)(n & 1);
+        for (elmrt_sim* s : b->sims) s->cur ^= (int)(n & 1);
+    };
+    if (k < nsteps && b->parity == 1) {   // graph replays start at parity 0
+        elmrt_status st = batch_enqueue_step(b, 1, b->stream);
+        if (st != ELMRT_OK) return st;
+        advance(1);
+        ++k;
+    }
+    if (b->use_graph && nsteps - k >= 2) {
+        if (!b->exec) {
+            elmrt_status st = batch_capture(b);
+            if (st != ELMRT_OK) return st;
+        }
+        for (; nsteps - k >= 2; k += 2) {
+            hipError_t e = hipGraphLaunch(b->exec, b->stream);
+            if (e != hipSuccess) return hip_fail(e, "hipGraphLaunch");
+            advance(2);
+        }
+    }
+    for (; k < nsteps; ++k) {
+        elmrt_status st = batch_enqueue_step(b, b->parity, b->stream);
+        if (st != ELMRT_OK) return st;
+        advance(1);
+    }
+    return ELMRT_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+elmrt_status elmrt_batch_workspace_bytes(int32_t count, size_t* bytes)
+{
+    if (count < 1) return fail(ELMRT_E_INVALID, "count must be >= 1");
+    if (!bytes) return fail(ELMRT_E_INVALID, "bytes is NULL");
+    *bytes = batch_table_bytes(count);
+    return ELMRT_OK;
+}
+
+elmrt_status elmrt_batch_create(elmrt_sim* const* sims, int32_t count, void* ws, size_t ws_bytes,
+                                elmrt_batch** out)
+{
+    if (!out) return fail(ELMRT_E_INVALID, "out is NULL");
+    *out = nullptr;
+    if (!sims || count < 1) return fail(ELMRT_E_INVALID, "no sims");
+    if (!ws || ((uintptr_t)ws % kAlign) != 0) return fail(ELMRT_E_INVALID, "workspace is NULL or not 256-byte aligned");
+    if (ws_bytes < batch_table_bytes(count)) return fail(ELMRT_E_INVALID, "workspace too small for the job table");
+    std::vector<elmrt_sim*> v(sims, sims + count);
+    for (int k = 0; k < count; ++k) {
+        const elmrt_sim* s = v[k];
+        if (!s) return fail(ELMRT_E_INVALID, "a sim is NULL");
+        if (!s->initialised) return fail(ELMRT_E_STATE, "a sim has not been initialised");
+        if (s->D != v[0]->D || s->L.fp64 != v[0]->L.fp64)
+            return fail(ELMRT_E_INVALID, "sims of a batch must share lattice and precision");
+        if (s->stream != v[0]->stream) return fail(ELMRT_E_INVALID, "sims of a batch must share the stream");
+        for (int j = 0; j < k; ++j)
+            if (v[j] == s) return fail(ELMRT_E_INVALID, "a sim appears twice in the batch");
+    }
+    elmrt_batch* b = new elmrt_batch;
+    b->sims = v;
+    b->D = v[0]->D;
+    b->fp64 = v[0]->L.fp64;
+    b->stream = v[0]->stream;
+    b->djobs = (elmrt::BatchJob*)ws;
+    elmrt_status st = batch_build(b);
+    if (st != ELMRT_OK) {
+        delete b;
+        return st;
+    }
+    *out = b;
+    return ELMRT_OK;
+}
+
+elmrt_status elmrt_batch_step(elmrt_batch* b, int64_t nsteps)
+{
+    if (!b) return fail(ELMRT_E_INVALID, "batch is NULL");
+    if (nsteps < 0) return fail(ELMRT_E_INVALID, "nsteps < 0");
+    return batch_step_impl(b, nsteps);
+}
+
+elmrt_status elmrt_batch_set_graph(elmrt_batch* b, int32_t use_graph)
+{
+    if (!b) return fail(ELMRT_E_INVALID, "batch is NULL");
+    b->use_graph = use_graph != 0;
+    return ELMRT_OK;
+}
+
+elmrt_status elmrt_batch_autotune(elmrt_batch* b, int32_t trial_steps, int64_t* steps_taken)
+{
+    if (!b) return fail(ELMRT_E_INVALID, "batch is NULL");
+    if (trial_steps < 2) return fail(ELMRT_E_INVALID, "trial_steps must be >= 2");
+    int64_t taken = 0;
+    float best = 0.f;
+    std::vector<std::array<int, 3>> keep;
+    for (elmrt_sim* s : b->sims) keep.push_back({s->tx, s->ty, s->tm});
+    std::vector<std::array<int, 3>> arg = keep;
+    for (const auto& c : tiling_candidates(b->D)) {
+        for (elmrt_sim* s : b->sims) {
+            s->tx = c[0];
+            s->ty = c[1];
+            // no deeper than the grid: marching depth at most the last extent
+            s->tm = std::min(c[2], s->L.g.n[s->D - 1]);
+        }
+        elmrt_status st = batch_build(b);
+        if (st == ELMRT_OK) st = batch_step_impl(b, 2);   // first replay of a shape: not timed
+        float ms = 0.f;
+        if (st == ELMRT_OK) st = time_steps(b->stream, [&] { return batch_step_impl(b, trial_steps); }, &ms);
+        if (st != ELMRT_OK) return st;
+        taken += 2 + trial_steps;
+        if (best == 0.f || ms < best) {
+            best = ms;
+            arg.clear();
+            for (elmrt_sim* s : b->sims) arg.push_back({s->tx, s->ty, s->tm});
+        }
+    }
+    for (size_t k = 0; k < b->sims.size(); ++k) {
+        b->sims[k]->tx = arg[k][0];
+        b->sims[k]->ty = arg[k][1];
+        b->sims[k]->tm = arg[k][2];
+    }
+    elmrt_status st = batch_build(b);
+    if (st != ELMRT_OK) return st;
+    if (steps_taken) *steps_taken = taken;
+    return ELMRT_OK;
+}
+
+void elmrt_batch_destroy(elmrt_batch* b) { delete b; }
 
 void elmrt_destroy(elmrt_sim* s) { delete s; }
 

@@ -29,6 +29,23 @@ struct Phys {
     int entropic;  // 1: entropic gamma, 0: BGK
 };
 
+// One simulation of a batch: its buffers, grid, constants and tilings, and the
+// first workgroup index of its tiles in the batched moment and collision
+// launches.  The table lives in device memory; every field is read uniformly.
+struct BatchJob {
+    const void* buf[2];   // population buffers
+    void* rho;
+    void* q;
+    unsigned* flag;
+    Grid g;
+    Phys<double> ph;
+    int mbx, mby, mtm;    // moment-pass tiling
+    int cbx, cby, ctm;    // collision tiling
+    int mfirst, cfirst;   // first workgroup of this job in each launch
+    int cur0;             // buffer holding f at batch parity 0
+    int pad;
+};
+
 // Every launcher returns the launch status (hipGetLastError after the launch).
 // T is float or double, selected by the 'fp64' flag; D is 2 or 3.
 struct Launch {
@@ -59,5 +76,22 @@ hipError_t launch_pull(const Launch& L, const void* cur, void* out);
 
 // Tile shapes compiled for the collision kernel.
 bool collide_shape_supported(int D, int tx, int ty);
+
+// Tiling arithmetic shared by the single and batched launches.
+struct Tiling {
+    int bx, by, bm;
+    long long blocks;
+};
+Tiling macro_tiling(int D, const Grid& g);
+Tiling collide_tiling(int D, const Grid& g, int tx, int ty, int tm);
+constexpr int kMacroTX = 256, kMacroTM = 8;
+
+// Batched launches over a device job table (jobs sorted by first workgroup).
+// All jobs share the lattice, the precision and, for the collision, the tile
+// shape (tx, ty); 'blocks' is the total workgroup count of the launch.
+hipError_t launch_macro_batch(int D, int fp64, const BatchJob* jobs, int njobs, long long blocks, int parity,
+                              hipStream_t stream);
+hipError_t launch_collide_batch(int D, int fp64, int tx, int ty, const BatchJob* jobs, int njobs,
+                                long long blocks, int parity, hipStream_t stream);
 
 }  // namespace elmrt

@@ -673,9 +673,8 @@ struct TileCoords {
 };
 
 template <int D, int TX, int TY>
-__device__ __forceinline__ TileCoords tile_of(const Grid& g, int bx, int by, int tm)
+__device__ __forceinline__ TileCoords tile_of(const Grid& g, int b, int bx, int by, int tm)
 {
-    int b = blockIdx.x;
     TileCoords t;
     const int xb = b % bx;
     b /= bx;
@@ -693,12 +692,12 @@ __device__ __forceinline__ TileCoords tile_of(const Grid& g, int bx, int by, int
 
 // Moment pass: rho and the Phi flux q_a = rho u_a^3 of every cell.
 template <int D, typename T, int TX, int TY>
-__global__ __launch_bounds__(TX* TY) void k_macro(const T* __restrict__ cur, T* __restrict__ rho_out,
-                                                  T* __restrict__ q_out, unsigned* __restrict__ flag,
-                                                  Grid g, int bx, int by, int tm)
+__device__ __forceinline__ void macro_tile(int b, const T* __restrict__ cur, T* __restrict__ rho_out,
+                                           T* __restrict__ q_out, unsigned* __restrict__ flag, const Grid& g,
+                                           int bx, int by, int tm)
 {
     constexpr int Q = Lat<D>::Q;
-    const TileCoords t = tile_of<D, TX, TY>(g, bx, by, tm);
+    const TileCoords t = tile_of<D, TX, TY>(g, b, bx, by, tm);
     const int x = t.x0 + (int)threadIdx.x;
     const int y = (D == 3) ? t.y0 + (int)threadIdx.y : 0;
     if (x >= g.n[0] || (D == 3 && y >= g.n[1])) return;
@@ -737,9 +736,9 @@ struct CollideWaves {
     static constexpr int v = (D == 3 && sizeof(T) == 4) ? 3 : 1;
 };
 template <int D, typename T, int TX, int TY>
-__global__ __launch_bounds__(TX* TY) __attribute__((amdgpu_waves_per_eu(CollideWaves<D, T>::v))) void k_collide(const T* __restrict__ cur, T* __restrict__ nxt,
-                                                    const T* __restrict__ rho, const T* __restrict__ q,
-                                                    Grid g, Phys<double> ph, int bx, int by, int tm)
+__device__ __forceinline__ void collide_tile(int b, const T* __restrict__ cur, T* __restrict__ nxt,
+                                             const T* __restrict__ rho, const T* __restrict__ q, const Grid& g,
+                                             const Phys<double>& ph, int bx, int by, int tm)
 {
     constexpr int Q = Lat<D>::Q;
     constexpr int HX = TX + 4;
@@ -749,7 +748,7 @@ __global__ __launch_bounds__(TX* TY) __attribute__((amdgpu_waves_per_eu(CollideW
     constexpr int MA = D - 1;
     __shared__ V2<double> tile[5][HY][HX];   // rho and signed psi, FP64
 
-    const TileCoords t = tile_of<D, TX, TY>(g, bx, by, tm);
+    const TileCoords t = tile_of<D, TX, TY>(g, b, bx, by, tm);
     const int tx = threadIdx.x;
     const int ty = (D == 3) ? (int)threadIdx.y : 0;
     const int lid = threadIdx.x + TX * threadIdx.y;
@@ -926,6 +925,59 @@ __global__ __launch_bounds__(TX* TY) __attribute__((amdgpu_waves_per_eu(CollideW
     }
 }
 
+// Single-simulation entry points: one workgroup per tile.
+template <int D, typename T, int TX, int TY>
+__global__ __launch_bounds__(TX* TY) void k_macro(const T* __restrict__ cur, T* __restrict__ rho_out,
+                                                  T* __restrict__ q_out, unsigned* __restrict__ flag, Grid g,
+                                                  int bx, int by, int tm)
+{
+    macro_tile<D, T, TX, TY>((int)blockIdx.x, cur, rho_out, q_out, flag, g, bx, by, tm);
+}
+
+template <int D, typename T, int TX, int TY>
+__global__ __launch_bounds__(TX* TY) __attribute__((amdgpu_waves_per_eu(CollideWaves<D, T>::v))) void k_collide(
+    const T* __restrict__ cur, T* __restrict__ nxt, const T* __restrict__ rho, const T* __restrict__ q, Grid g,
+    Phys<double> ph, int bx, int by, int tm)
+{
+    collide_tile<D, T, TX, TY>((int)blockIdx.x, cur, nxt, rho, q, g, ph, bx, by, tm);
+}
+
+// Batched entry points: the workgroups of one launch cover the tiles of every
+// job of a batch table, job j owning the launch indices [first_j, first_{j+1}).
+// The job of a workgroup is found by binary search over the (uniform) table;
+// the state buffer holding f(t) alternates with the step parity.
+__device__ __forceinline__ int job_of(const BatchJob* __restrict__ jobs, int njobs, int b, int BatchJob::*first)
+{
+    int lo = 0, hi = njobs - 1;
+    while (lo < hi) {
+        const int mid = (lo + hi + 1) >> 1;
+        if (jobs[mid].*first <= b) lo = mid;
+        else hi = mid - 1;
+    }
+    return lo;
+}
+
+template <int D, typename T, int TX, int TY>
+__global__ __launch_bounds__(TX* TY) void k_macro_batch(const BatchJob* __restrict__ jobs, int njobs, int parity)
+{
+    const int b = (int)blockIdx.x;
+    const int j = job_of(jobs, njobs, b, &BatchJob::mfirst);
+    const BatchJob& J = jobs[j];
+    macro_tile<D, T, TX, TY>(b - J.mfirst, (const T*)J.buf[J.cur0 ^ parity], (T*)J.rho, (T*)J.q, J.flag, J.g,
+                             J.mbx, J.mby, J.mtm);
+}
+
+template <int D, typename T, int TX, int TY>
+__global__ __launch_bounds__(TX* TY) __attribute__((amdgpu_waves_per_eu(CollideWaves<D, T>::v))) void k_collide_batch(
+    const BatchJob* __restrict__ jobs, int njobs, int parity)
+{
+    const int b = (int)blockIdx.x;
+    const int j = job_of(jobs, njobs, b, &BatchJob::cfirst);
+    const BatchJob& J = jobs[j];
+    collide_tile<D, T, TX, TY>(b - J.cfirst, (const T*)J.buf[J.cur0 ^ parity], (T*)J.buf[J.cur0 ^ parity ^ 1],
+                               (const T*)J.rho, (const T*)J.q, J.g, J.ph, J.cbx, J.cby, J.ctm);
+}
+
 // Initial velocity shift: the fluid velocity of the exact-difference forcing
 // is u + F dt/(2 rho), so starting from a prescribed fluid velocity u0 needs
 // the bare velocity u0 - F(rho0)/(2 rho0) in f^eq.  F is the force of
@@ -1077,22 +1129,29 @@ FlatGrid flat_of(const Grid& g)
 }
 
 
+unsigned flat_blocks(const Grid& g) { return (unsigned)(((long long)g.N + 255) / 256); }
+
 template <int D, typename T, int TX, int TY>
 hipError_t collide_t(const Launch& L, int tm, const void* cur, void* nxt, const void* rho, const void* q,
                      const Phys<double>& ph)
 {
-    const Grid& g = L.g;
-    const int bx = (g.n[0] + TX - 1) / TX;
-    const int by = (D == 3) ? (g.n[1] + TY - 1) / TY : 1;
-    const int nm = g.n[D - 1];
-    const int bm = (nm + tm - 1) / tm;
-    const long long blocks = (long long)bx * by * bm;
-    if (blocks <= 0 || blocks > 0x7fffffffLL) return hipErrorInvalidConfiguration;
-    hipLaunchKernelGGL((k_collide<D, T, TX, TY>), dim3((unsigned)blocks), dim3(TX, TY), 0, L.stream,
-                       (const T*)cur, (T*)nxt, (const T*)rho, (const T*)q, g, ph, bx, by, tm);
+    const Tiling t = collide_tiling(D, L.g, TX, TY, tm);
+    if (t.blocks <= 0 || t.blocks > 0x7fffffffLL) return hipErrorInvalidConfiguration;
+    hipLaunchKernelGGL((k_collide<D, T, TX, TY>), dim3((unsigned)t.blocks), dim3(TX, TY), 0, L.stream,
+                       (const T*)cur, (T*)nxt, (const T*)rho, (const T*)q, L.g, ph, t.bx, t.by, tm);
     return hipGetLastError();
 }
 
+template <int D, typename T, int TX, int TY>
+hipError_t collide_batch_t(const BatchJob* jobs, int njobs, long long blocks, int parity, hipStream_t stream)
+{
+    if (blocks <= 0 || blocks > 0x7fffffffLL || njobs < 1) return hipErrorInvalidConfiguration;
+    hipLaunchKernelGGL((k_collide_batch<D, T, TX, TY>), dim3((unsigned)blocks), dim3(TX, TY), 0, stream, jobs,
+                       njobs, parity);
+    return hipGetLastError();
+}
+
+// The compiled collision tile shapes, for the single and the batched launch.
 template <int D, typename T>
 hipError_t collide_dispatch(const Launch& L, int tx, int ty, int tm, const void* cur, void* nxt,
                             const void* rho, const void* q, const Phys<double>& ph)
@@ -1114,7 +1173,45 @@ hipError_t collide_dispatch(const Launch& L, int tx, int ty, int tm, const void*
     }
 }
 
-unsigned flat_blocks(const Grid& g) { return (unsigned)(((long long)g.N + 255) / 256); }
+template <int D, typename T>
+hipError_t collide_batch_dispatch(int tx, int ty, const BatchJob* jobs, int njobs, long long blocks, int parity,
+                                  hipStream_t stream)
+{
+    if constexpr (D == 2) {
+        if (ty != 1) return hipErrorInvalidValue;
+        switch (tx) {
+        case 64: return collide_batch_t<D, T, 64, 1>(jobs, njobs, blocks, parity, stream);
+        case 128: return collide_batch_t<D, T, 128, 1>(jobs, njobs, blocks, parity, stream);
+        case 256: return collide_batch_t<D, T, 256, 1>(jobs, njobs, blocks, parity, stream);
+        default: return hipErrorInvalidValue;
+        }
+    } else {
+        if (tx == 64 && ty == 4) return collide_batch_t<D, T, 64, 4>(jobs, njobs, blocks, parity, stream);
+        if (tx == 64 && ty == 2) return collide_batch_t<D, T, 64, 2>(jobs, njobs, blocks, parity, stream);
+        if (tx == 32 && ty == 8) return collide_batch_t<D, T, 32, 8>(jobs, njobs, blocks, parity, stream);
+        if (tx == 128 && ty == 2) return collide_batch_t<D, T, 128, 2>(jobs, njobs, blocks, parity, stream);
+        return hipErrorInvalidValue;
+    }
+}
+
+template <int D, typename T>
+hipError_t macro_t(const Launch& L, const void* cur, void* rho, void* q, unsigned* flag)
+{
+    const Tiling t = macro_tiling(D, L.g);
+    if (t.blocks <= 0 || t.blocks > 0x7fffffffLL) return hipErrorInvalidConfiguration;
+    hipLaunchKernelGGL((k_macro<D, T, kMacroTX, 1>), dim3((unsigned)t.blocks), dim3(kMacroTX, 1), 0, L.stream,
+                       (const T*)cur, (T*)rho, (T*)q, flag, L.g, t.bx, t.by, kMacroTM);
+    return hipGetLastError();
+}
+
+template <int D, typename T>
+hipError_t macro_batch_t(const BatchJob* jobs, int njobs, long long blocks, int parity, hipStream_t stream)
+{
+    if (blocks <= 0 || blocks > 0x7fffffffLL || njobs < 1) return hipErrorInvalidConfiguration;
+    hipLaunchKernelGGL((k_macro_batch<D, T, kMacroTX, 1>), dim3((unsigned)blocks), dim3(kMacroTX, 1), 0, stream,
+                       jobs, njobs, parity);
+    return hipGetLastError();
+}
 
 }  // namespace
 
@@ -1124,31 +1221,36 @@ bool collide_shape_supported(int D, int tx, int ty)
     return (tx == 64 && ty == 4) || (tx == 64 && ty == 2) || (tx == 32 && ty == 8) || (tx == 128 && ty == 2);
 }
 
-template <int D, typename T, int TX, int TY>
-hipError_t macro_t(const Launch& L, int tm, const void* cur, void* rho, void* q, unsigned* flag)
-{
-    const Grid& g = L.g;
-    const int bx = (g.n[0] + TX - 1) / TX;
-    const int by = (D == 3) ? (g.n[1] + TY - 1) / TY : 1;
-    const int bm = (g.n[D - 1] + tm - 1) / tm;
-    const long long blocks = (long long)bx * by * bm;
-    if (blocks <= 0 || blocks > 0x7fffffffLL) return hipErrorInvalidConfiguration;
-    hipLaunchKernelGGL((k_macro<D, T, TX, TY>), dim3((unsigned)blocks), dim3(TX, TY), 0, L.stream, (const T*)cur,
-                       (T*)rho, (T*)q, flag, g, bx, by, tm);
-    return hipGetLastError();
-}
-
 // The moment pass takes whole rows of up to 256 cells per workgroup: the
 // x-shifted pulls of a row then touch only the row's own cache lines (the
 // periodic wrap stays in the row), where 64-cell segments share a line with
 // the neighbouring segment at each end.
+Tiling macro_tiling(int D, const Grid& g)
+{
+    Tiling t;
+    t.bx = (g.n[0] + kMacroTX - 1) / kMacroTX;
+    t.by = (D == 3) ? g.n[1] : 1;
+    t.bm = (g.n[D - 1] + kMacroTM - 1) / kMacroTM;
+    t.blocks = (long long)t.bx * t.by * t.bm;
+    return t;
+}
+
+Tiling collide_tiling(int D, const Grid& g, int tx, int ty, int tm)
+{
+    Tiling t;
+    t.bx = (g.n[0] + tx - 1) / tx;
+    t.by = (D == 3) ? (g.n[1] + ty - 1) / ty : 1;
+    t.bm = (g.n[D - 1] + tm - 1) / tm;
+    t.blocks = (long long)t.bx * t.by * t.bm;
+    return t;
+}
+
 hipError_t launch_macro(const Launch& L, const void* cur, void* rho, void* q, unsigned* flag)
 {
-    constexpr int TM = 8;
-    if (L.D == 2 && !L.fp64) return macro_t<2, float, 256, 1>(L, TM, cur, rho, q, flag);
-    if (L.D == 2) return macro_t<2, double, 256, 1>(L, TM, cur, rho, q, flag);
-    if (!L.fp64) return macro_t<3, float, 256, 1>(L, TM, cur, rho, q, flag);
-    return macro_t<3, double, 256, 1>(L, TM, cur, rho, q, flag);
+    if (L.D == 2 && !L.fp64) return macro_t<2, float>(L, cur, rho, q, flag);
+    if (L.D == 2) return macro_t<2, double>(L, cur, rho, q, flag);
+    if (!L.fp64) return macro_t<3, float>(L, cur, rho, q, flag);
+    return macro_t<3, double>(L, cur, rho, q, flag);
 }
 
 hipError_t launch_collide(const Launch& L, int tx, int ty, int tm, const void* cur, void* nxt,
@@ -1159,6 +1261,24 @@ hipError_t launch_collide(const Launch& L, int tx, int ty, int tm, const void* c
     if (L.D == 2) return collide_dispatch<2, double>(L, tx, ty, tm, cur, nxt, rho, q, ph);
     if (!L.fp64) return collide_dispatch<3, float>(L, tx, ty, tm, cur, nxt, rho, q, ph);
     return collide_dispatch<3, double>(L, tx, ty, tm, cur, nxt, rho, q, ph);
+}
+
+hipError_t launch_macro_batch(int D, int fp64, const BatchJob* jobs, int njobs, long long blocks, int parity,
+                              hipStream_t stream)
+{
+    if (D == 2 && !fp64) return macro_batch_t<2, float>(jobs, njobs, blocks, parity, stream);
+    if (D == 2) return macro_batch_t<2, double>(jobs, njobs, blocks, parity, stream);
+    if (!fp64) return macro_batch_t<3, float>(jobs, njobs, blocks, parity, stream);
+    return macro_batch_t<3, double>(jobs, njobs, blocks, parity, stream);
+}
+
+hipError_t launch_collide_batch(int D, int fp64, int tx, int ty, const BatchJob* jobs, int njobs,
+                                long long blocks, int parity, hipStream_t stream)
+{
+    if (D == 2 && !fp64) return collide_batch_dispatch<2, float>(tx, ty, jobs, njobs, blocks, parity, stream);
+    if (D == 2) return collide_batch_dispatch<2, double>(tx, ty, jobs, njobs, blocks, parity, stream);
+    if (!fp64) return collide_batch_dispatch<3, float>(tx, ty, jobs, njobs, blocks, parity, stream);
+    return collide_batch_dispatch<3, double>(tx, ty, jobs, njobs, blocks, parity, stream);
 }
 
 hipError_t launch_shift_velocity(const Launch& L, const double* rho0, double* u0, const Phys<double>& ph)

@@ -64,6 +64,14 @@ _SIGS = {
     "elmrt_velocities": (ctypes.c_int32, [ctypes.c_int32, ctypes.POINTER(ctypes.c_int32)]),
     "elmrt_coexistence": (ctypes.c_int, [ctypes.POINTER(elmrt_params), _dp, _dp, _dp]),
     "elmrt_set_tiling": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_int32, ctypes.c_int32, ctypes.c_int32]),
+    "elmrt_autotune": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_int32, ctypes.POINTER(ctypes.c_int64)]),
+    "elmrt_batch_workspace_bytes": (ctypes.c_int, [ctypes.c_int32, ctypes.POINTER(ctypes.c_size_t)]),
+    "elmrt_batch_create": (ctypes.c_int, [ctypes.POINTER(ctypes.c_void_p), ctypes.c_int32, ctypes.c_void_p,
+                                          ctypes.c_size_t, ctypes.POINTER(ctypes.c_void_p)]),
+    "elmrt_batch_step": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_int64]),
+    "elmrt_batch_set_graph": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_int32]),
+    "elmrt_batch_autotune": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_int32, ctypes.POINTER(ctypes.c_int64)]),
+    "elmrt_batch_destroy": (None, [ctypes.c_void_p]),
     "elmrt_destroy": (None, [ctypes.c_void_p]),
     "elmrt_last_error": (ctypes.c_char_p, []),
 }
@@ -227,6 +235,44 @@ def elmrt_set_tiling(sim: int, tx: int, ty: int, tm: int) -> None:
     _check(lib().elmrt_set_tiling(ctypes.c_void_p(sim), int(tx), int(ty), int(tm)))
 
 
+def elmrt_autotune(sim: int, trial_steps: int) -> int:
+    taken = ctypes.c_int64()
+    _check(lib().elmrt_autotune(ctypes.c_void_p(sim), int(trial_steps), ctypes.byref(taken)))
+    return taken.value
+
+
+def elmrt_batch_workspace_bytes(count: int) -> int:
+    out = ctypes.c_size_t()
+    _check(lib().elmrt_batch_workspace_bytes(int(count), ctypes.byref(out)))
+    return out.value
+
+
+def elmrt_batch_create(sims, workspace_ptr: int, workspace_bytes: int) -> int:
+    arr = (ctypes.c_void_p * len(sims))(*[ctypes.c_void_p(h) for h in sims])
+    h = ctypes.c_void_p()
+    _check(lib().elmrt_batch_create(arr, len(sims), ctypes.c_void_p(workspace_ptr), workspace_bytes,
+                                    ctypes.byref(h)))
+    return h.value
+
+
+def elmrt_batch_step(batch: int, nsteps: int) -> None:
+    _check(lib().elmrt_batch_step(ctypes.c_void_p(batch), int(nsteps)))
+
+
+def elmrt_batch_set_graph(batch: int, use_graph: bool) -> None:
+    _check(lib().elmrt_batch_set_graph(ctypes.c_void_p(batch), int(bool(use_graph))))
+
+
+def elmrt_batch_autotune(batch: int, trial_steps: int) -> int:
+    taken = ctypes.c_int64()
+    _check(lib().elmrt_batch_autotune(ctypes.c_void_p(batch), int(trial_steps), ctypes.byref(taken)))
+    return taken.value
+
+
+def elmrt_batch_destroy(batch: int) -> None:
+    lib().elmrt_batch_destroy(ctypes.c_void_p(batch))
+
+
 def elmrt_destroy(sim: int) -> None:
     lib().elmrt_destroy(ctypes.c_void_p(sim))
 
@@ -277,9 +323,49 @@ class Simulation:
     def set_tiling(self, tx, ty, tm):
         elmrt_set_tiling(self.handle, tx, ty, tm)
 
+    def autotune(self, trial_steps: int = 4) -> int:
+        return elmrt_autotune(self.handle, trial_steps)
+
     def close(self):
         if self.handle:
             elmrt_destroy(self.handle)
+            self.handle = 0
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+class Batch:
+    """Simulations of one lattice, precision and stream advanced together
+    (one launch per pass and step, pairs of steps replayed from a HIP graph).
+    The members stay usable through their own handles; the job table lives in
+    a torch-allocated device buffer owned by this object."""
+
+    def __init__(self, sims, device: str = "cuda:0"):
+        import torch
+
+        self.sims = list(sims)
+        nbytes = elmrt_batch_workspace_bytes(len(self.sims))
+        raw = torch.empty(nbytes + 256, dtype=torch.uint8, device=torch.device(device))
+        off = (-raw.data_ptr()) % 256
+        self.workspace = raw[off: off + nbytes]
+        self.handle = elmrt_batch_create([s.handle for s in self.sims], self.workspace.data_ptr(), nbytes)
+
+    def step(self, nsteps: int):
+        elmrt_batch_step(self.handle, nsteps)
+
+    def set_graph(self, use_graph: bool):
+        elmrt_batch_set_graph(self.handle, use_graph)
+
+    def autotune(self, trial_steps: int = 4) -> int:
+        return elmrt_batch_autotune(self.handle, trial_steps)
+
+    def close(self):
+        if self.handle:
+            elmrt_batch_destroy(self.handle)
             self.handle = 0
 
     def __del__(self):

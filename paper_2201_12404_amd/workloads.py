@@ -41,6 +41,55 @@ COEX = {
 TR_RATIO_1000 = 0.592454
 KAPPA_W5_RATIO_1000 = 0.01219     # square-gradient kappa~ for W = 5 at ratio 1000, EOS set B
 
+# Maxwell coexistence (rho_v, rho_l) of EOS set B by reduced temperature:
+# T/Tc = 0.60 .. 0.90 in steps of 0.01, and the temperatures of the density
+# ratios 1000, 100, 10 (written by tests/golden/make_coexistence_table.py).
+COEX_B_TABLE = {
+    0.6: (0.010256254041444899, 8.746713113967818),
+    0.61: (0.012499227237872022, 8.689831850259097),
+    0.62: (0.015120352686928098, 8.631415610172784),
+    0.63: (0.01816437335895818, 8.571403009734869),
+    0.64: (0.021679157297824013, 8.509728867127127),
+    0.65: (0.02571584579789224, 8.446323881152825),
+    0.66: (0.030329039696676947, 8.381114270987307),
+    0.67: (0.03557703115829154, 8.314021371206149),
+    0.68: (0.04152208902592476, 8.244961174947885),
+    0.69: (0.04823080681247406, 8.17384381666729),
+    0.7: (0.055774523760970016, 8.100572984196372),
+    0.71: (0.06422983124239237, 8.025045247658579),
+    0.72: (0.07367917919673458, 7.94714929004974),
+    0.73: (0.08421160053251234, 7.866765020838681),
+    0.74: (0.0959235756065201, 7.783762549520429),
+    0.75: (0.10892006441815894, 7.698000990363289),
+    0.76: (0.12331574139881563, 7.609327062193561),
+    0.77: (0.1392364772558622, 7.517573437353024),
+    0.78: (0.15682112509460644, 7.42255678108655),
+    0.79: (0.17622368521466736, 7.324075405339272),
+    0.8: (0.1976159463471271, 7.2219064374712225),
+    0.81: (0.2211907333132178, 7.115802372079132),
+    0.82: (0.24716593613455512, 7.005486828954025),
+    0.83: (0.27578955963457163, 6.890649276069038),
+    0.84: (0.3073461251417693, 6.770938383778612),
+    0.85: (0.3421648924312004, 6.645953539718899),
+    0.86: (0.38063057583931903, 6.515233847907654),
+    0.87: (0.4231975463981391, 6.3782436174044275),
+    0.88: (0.4704090166979872, 6.234352840763261),
+    0.89: (0.5229235325754982, 6.082810334811679),
+    0.9: (0.5815525016166778, 5.922705810032623),
+    0.592454: (0.008788568917849803, 8.78865484765582),
+    0.725237: (0.07905400211939459, 7.905370373963834),
+    0.901356: (0.5900262283184834, 5.900277847492134),
+}
+TR_OF_RATIO = {1000: 0.592454, 100: 0.725237, 10: 0.901356}
+
+
+def kappa_w5(tr: float) -> float:
+    """kappa~ giving an equilibrium interface width of ~5 for EOS set B at
+    T/Tc = tr: the square-gradient values 0.01219, 0.007348, 0.005019 and
+    0.002270 (T/Tc = 0.5925, 0.7252, 0.8, 0.9014) follow
+    0.01219 ((1 - tr) / 0.407546)^1.25 within 8%."""
+    return KAPPA_W5_RATIO_1000 * ((1.0 - tr) / (1.0 - TR_RATIO_1000)) ** 1.25
+
 
 @dataclass(frozen=True)
 class Workload:
@@ -137,3 +186,67 @@ IMPACT_3D = Workload(
     eos=EOS_B, T_over_Tc=TR_RATIO_1000, kappa_tilde=KAPPA_W5_RATIO_1000, nu_liquid=0.005,
     nu_vapour=_nu_vapour(0.005, _rv_b, _rl_b), rho_v=_rv_b, rho_l=_rl_b, kind="impact",
     radius=40.0, width=7.0, film=8.0, centre=(128.0, 128.0, 8.0 + 40.0 + 14.0), u_impact=0.04, steps=10000)
+
+
+# ------------------------------------------------------------- job sets
+
+
+def batch_static_drops(count: int = 64, seed: int = 0, steps: int = 2000, lo: int = 64, hi: int = 512):
+    """Independent D2Q9 static drops of uneven size (FP32): edge N uniform in
+    {lo..hi}, radius 0.2 N, T/Tc uniform on the 0.60 .. 0.90 grid of the
+    coexistence table, EOS set B, kappa~ for W ~ 5, nu = 0.02 in both phases,
+    velocity noise 1e-4 (seed k for job k), periodic."""
+    rng = np.random.default_rng(seed)
+    grid = [round(0.60 + 0.01 * k, 2) for k in range(31)]
+    jobs = []
+    for k in range(count):
+        N = int(rng.integers(lo, hi + 1))
+        tr = grid[int(rng.integers(0, len(grid)))]
+        rv, rl = COEX_B_TABLE[tr]
+        jobs.append(Workload(
+            name=f"drop-{k}-d2q9-{N}-fp32", lattice=0, n=(N, N), bc=(0, 0), precision=0, eos=EOS_B,
+            T_over_Tc=tr, kappa_tilde=kappa_w5(tr), nu_liquid=0.02, nu_vapour=0.02, rho_v=rv, rho_l=rl,
+            kind="drop", radius=0.2 * N, centre=((N - 1) / 2, (N - 1) / 2), noise=1e-4, seed=k, steps=steps))
+    return jobs
+
+
+def impact_job(D: int, N: int, ratio: int, u0: float, steps: int, k: int = 0) -> Workload:
+    """A drop impact of the served mix: D2Q9 on N x N (x periodic, walls in
+    y) or D3Q27 on N^3 (x, y periodic, walls in z); drop diameter 0.3125 N,
+    film max(0.1 D, 2W), gap 2W, W = 7, nu_l = 0.005, nu_v = nu_l max(1,
+    ratio / 55), FP32."""
+    tr = TR_OF_RATIO[ratio]
+    rv, rl = COEX_B_TABLE[tr]
+    W = 7.0
+    R = 0.3125 * N / 2
+    h = max(0.1 * 2 * R, 2 * W)
+    zc = h + R + 2 * W
+    nu_l = 0.005
+    nu_v = nu_l * max(1.0, ratio / 55.0)
+    if D == 2:
+        n, bc, c = (N, N), (0, 1), ((N - 1) / 2, zc)
+    else:
+        n, bc, c = (N, N, N), (0, 0, 1), ((N - 1) / 2, (N - 1) / 2, zc)
+    return Workload(
+        name=f"impact-{k}-d{D}q{9 if D == 2 else 27}-{N}-r{ratio}-fp32", lattice=0 if D == 2 else 1, n=n, bc=bc,
+        precision=0, eos=EOS_B, T_over_Tc=tr, kappa_tilde=kappa_w5(tr), nu_liquid=nu_l, nu_vapour=nu_v,
+        rho_v=rv, rho_l=rl, kind="impact", radius=R, width=W, film=h, centre=c, u_impact=u0, seed=k, steps=steps)
+
+
+def served_stream(count: int = 200, rate: float = 20.0, seed: int = 0):
+    """Seeded Poisson stream of impact jobs: (arrival time [s], Workload).
+    Half D2Q9 with N uniform in {128..1024}, half D3Q27 with N in {64..192};
+    density ratio from {10, 100, 1000}; impact speed uniform in [0.02, 0.06];
+    2000 .. 10000 steps."""
+    rng = np.random.default_rng(seed)
+    t = 0.0
+    out = []
+    for k in range(count):
+        t += float(rng.exponential(1.0 / rate))
+        D = 2 if rng.random() < 0.5 else 3
+        N = int(rng.integers(128, 1025)) if D == 2 else int(rng.integers(64, 193))
+        ratio = int(rng.choice([10, 100, 1000]))
+        u0 = float(rng.uniform(0.02, 0.06))
+        steps = int(rng.integers(2000, 10001))
+        out.append((t, impact_job(D, N, ratio, u0, steps, k)))
+    return out

@@ -116,3 +116,26 @@ def test_no_cpu_fallback_in_product_package():
                 txt = open(os.path.join(dp, fn)).read()
                 assert "import oracle" not in txt and "from oracle" not in txt, fn
                 assert "elmrt_oracle" not in txt, fn
+
+
+def test_batch_workspace_bytes():
+    assert E.elmrt_batch_workspace_bytes(1) >= 128
+    assert E.elmrt_batch_workspace_bytes(64) >= 64 * 128
+    assert E.elmrt_batch_workspace_bytes(64) % 256 == 0
+    with pytest.raises(E.ElmrtError):
+        E.elmrt_batch_workspace_bytes(0)
+
+
+def test_batch_create_rejects_bad_arguments_without_a_device():
+    # every argument check precedes any device call
+    with pytest.raises(E.ElmrtError, match="no sims"):
+        E.elmrt_batch_create([], 256, 1 << 20)
+    with pytest.raises(E.ElmrtError, match="aligned"):
+        E.elmrt_batch_create([1], 8, 1 << 20)
+
+
+def test_plane_block_limit():
+    # Q x cells per plane x value size must stay below 2^31 bytes
+    p = E.Params(lattice=1, n=(5000, 5000, 4), precision=1, bc=(0, 0, 1))
+    with pytest.raises(E.ElmrtError, match="plane block"):
+        E.elmrt_workspace_bytes(p)
