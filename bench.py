@@ -88,6 +88,121 @@ def cpu_baseline(w, budget_s: float = 20.0):
                       f"(FP64 oracle, OpenMP over cells), {elapsed:.1f} s"}
 
 
+def batched_vs_plain(steps: int = 2000, trial_steps: int = 4):
+    """64 uneven D2Q9 static drops (FP32), each for 'steps' steps: one after
+    the other through the single-simulation path, then all together as one
+    batch (autotuned tiling, graph replay).  Aggregate MLUPS of both; the
+    autotuning trials are steps of the run and are timed with it."""
+    import torch
+
+    from paper_2201_12404_amd import elmrt as E
+    from paper_2201_12404_amd import workloads as W
+
+    jobs = W.batch_static_drops(count=64, seed=0, steps=steps)
+    cells = sum(j.N for j in jobs)
+
+    def fresh():
+        sims = []
+        for j in jobs:
+            sim = E.Simulation(E.params_for(j))
+            sim.init_fields(*W.initial_fields(j))
+            sims.append(sim)
+        torch.cuda.synchronize()
+        return sims
+
+    sims = fresh()
+    t0 = time.perf_counter()
+    for sim in sims:
+        sim.step(steps)
+    torch.cuda.synchronize()
+    t_plain = time.perf_counter() - t0
+    for sim in sims:
+        sim.close()
+    sims = fresh()
+    b = E.Batch(sims)
+    t0 = time.perf_counter()
+    taken = b.autotune(trial_steps)
+    b.step(steps - taken)
+    torch.cuda.synchronize()
+    t_batch = time.perf_counter() - t0
+    b.close()
+    for sim in sims:
+        sim.close()
+    return {"workload": f"64 D2Q9 static drops, edges 64..512, {cells} cells, {steps} steps, FP32",
+            "plain_mlups": round(cells * steps / t_plain / 1e6, 1), "plain_s": round(t_plain, 3),
+            "batched_mlups": round(cells * steps / t_batch / 1e6, 1), "batched_s": round(t_batch, 3),
+            "autotune_steps": taken, "speedup": round(t_plain / t_batch, 2),
+            "accuracy": "bitwise equal to the plain path (same kernels)"}
+
+
+def served_vs_plain(count: int, step_scale: float, pool_gib: float = 16.0, chunk: int = 200):
+    """The served impact stream (seeded Poisson arrivals, 20 jobs/s, D2Q9 and
+    D3Q27 drop impacts of mixed size, density ratio and speed), first 'count'
+    jobs with step counts scaled by 'step_scale'.  Served: arrivals replayed
+    in real time into the request loop (admission by footprint into a
+    'pool_gib' GiB pool, resident jobs advanced in shared batches of 'chunk'
+    steps).  Plain: each job alone through the single-simulation path; its
+    FIFO latencies follow from the measured service times and the same
+    arrival times.  Latency = arrival to completion."""
+    import numpy as np
+    import torch
+
+    from paper_2201_12404_amd import elmrt as E
+    from paper_2201_12404_amd import workloads as W
+
+    stream = W.served_stream(count=count, rate=20.0, seed=0)
+    jobs = [(t, w, max(1, int(round(w.steps * step_scale)))) for t, w in stream]
+    lu_total = sum(w.N * n for _, w, n in jobs)
+
+    # plain: service times of each job alone
+    service = []
+    for _, w, n in jobs:
+        sim = E.Simulation(E.params_for(w))
+        sim.init_fields(*W.initial_fields(w))
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        sim.step(n)
+        sim.read_macros()
+        service.append(time.perf_counter() - t0)
+        sim.close()
+    finish, lat = 0.0, []
+    for (t, _, _), sv in zip(jobs, service):
+        finish = max(finish, t) + sv
+        lat.append(finish - t)
+    plain = {"p50_s": round(float(np.percentile(lat, 50)), 3), "p99_s": round(float(np.percentile(lat, 99)), 3),
+             "mlups": round(lu_total / sum(service) / 1e6, 1), "busy_s": round(sum(service), 3)}
+
+    # served: real-time replay of the arrivals
+    inputs = [W.initial_fields(w) for _, w, _ in jobs]
+    srv = E.Server(pool_bytes=int(pool_gib * (1 << 30)), chunk_steps=chunk)
+    ids = [None] * len(jobs)
+    t_start = time.monotonic()
+    k = 0
+    while True:
+        now = time.monotonic() - t_start
+        while k < len(jobs) and jobs[k][0] <= now:
+            _, w, n = jobs[k]
+            ids[k] = srv.submit(E.params_for(w), inputs[k][0], inputs[k][1], n)
+            k += 1
+        q, r = srv.run(1)
+        if k == len(jobs) and q == 0 and r == 0:
+            break
+        if q == 0 and r == 0 and k < len(jobs):
+            time.sleep(max(0.0, min(0.01, jobs[k][0] - (time.monotonic() - t_start))))
+    t_end = time.monotonic() - t_start
+    lat_s = []
+    for (t, _, _), jid in zip(jobs, ids):
+        st, times, _ = srv.job(jid)
+        lat_s.append(times[2] - (t_start + t))
+    srv.close()
+    served = {"p50_s": round(float(np.percentile(lat_s, 50)), 3), "p99_s": round(float(np.percentile(lat_s, 99)), 3),
+              "mlups": round(lu_total / t_end / 1e6, 1), "makespan_s": round(t_end, 3)}
+    return {"workload": f"first {count} jobs of the served stream (seed 0, 20 jobs/s), steps x {step_scale}, "
+                        f"{lu_total:.3e} lattice updates, FP32",
+            "served": served, "plain": plain,
+            "accuracy": "bitwise equal to the job run alone (tested)"}
+
+
 def copy_probe(nbytes: int = 1 << 30):
     """A plain device copy kernel of known size (read nbytes, write nbytes),
     for calibrating the rocprofv3 FETCH_SIZE / WRITE_SIZE counters."""
@@ -107,6 +222,9 @@ def main():
     ap.add_argument("--cpu-budget", type=float, default=20.0)
     ap.add_argument("--copy-probe", action="store_true", help="also run a 1 GiB copy kernel (counter calibration)")
     ap.add_argument("--tile", type=str, default="", help="tx,ty,tm of the collision kernel")
+    ap.add_argument("--no-batched", action="store_true", help="skip the batched and served comparisons")
+    ap.add_argument("--serve-jobs", type=int, default=24, help="jobs of the served stream to replay")
+    ap.add_argument("--serve-step-scale", type=float, default=0.1, help="scale of the served jobs' step counts")
     args = ap.parse_args()
 
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
@@ -184,6 +302,11 @@ def main():
     }
     if args.copy_probe:
         copy_probe()
+    if not args.no_batched:
+        print("[bench] batched vs plain (64 static drops)", file=sys.stderr, flush=True)
+        out["batched"] = batched_vs_plain()
+        print("[bench] served vs plain", file=sys.stderr, flush=True)
+        out["served"] = served_vs_plain(args.serve_jobs, args.serve_step_scale)
     if not args.no_cpu_baseline:
         print("[bench] cpu baseline", file=sys.stderr, flush=True)
         out["cpu_baseline"] = cpu_baseline(w, args.cpu_budget)

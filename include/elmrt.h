@@ -186,6 +186,58 @@ void elmrt_batch_destroy(elmrt_batch* b);
 /* Release the handle (not the workspace).  NULL is ignored. */
 void elmrt_destroy(elmrt_sim* s);
 
+/* ---- Serving: a request loop over resident simulations ------------------
+ *
+ * Jobs (a problem statement as for elmrt_create, initial fields as for
+ * elmrt_init_fields, a step count) are queued by elmrt_server_submit and
+ * admitted in arrival order while their workspace fits a caller-owned device
+ * pool (first fit; a job that does not fit waits, and so do the ones behind
+ * it).  Admitted jobs stay resident and are advanced in rounds by
+ * elmrt_server_run: in every round the resident jobs of each lattice and
+ * precision form one batch (the elmrt_batch_* entry points) that advances by
+ * chunk_steps, or by the fewest steps any member still needs, so every job
+ * stops exactly at its step count; finished jobs are read out (fields and
+ * sums kept on the host until elmrt_server_result) and their memory goes back
+ * to the pool before the next admission.  A job's result is bitwise the same
+ * as the same simulation run alone.  The server owns its job records; the
+ * pool and the stream are the caller's and must outlive it.  Not thread-safe:
+ * one thread drives a server. */
+typedef struct elmrt_server elmrt_server;
+
+/* dev_pool: device memory (256-byte aligned, >= 4096 bytes) the server carves
+ * job workspaces and batch tables from; stream: hipStream_t or NULL. */
+elmrt_status elmrt_server_create(void* dev_pool, size_t pool_bytes, void* stream, int64_t chunk_steps,
+                                 elmrt_server** out);
+
+/* Queue a job; the fields (rho0[N], u0[D][N], FP64 host) are copied.  Fails
+ * with ELMRT_E_INVALID when elmrt_create would reject p.  *job_id > 0. */
+elmrt_status elmrt_server_submit(elmrt_server* s, const elmrt_params* p, const double* rho0, const double* u0,
+                                 int64_t steps, int64_t* job_id);
+
+/* Run up to 'rounds' rounds (admission, one batched advance per lattice and
+ * precision, retirement); returns early when no job is queued or resident.
+ * *queued, *resident (may be NULL) count the jobs waiting and on the device. */
+elmrt_status elmrt_server_run(elmrt_server* s, int32_t rounds, int32_t* queued, int32_t* resident);
+
+/* State of a job (0 queued, 1 resident, 2 done, 3 failed), its submit /
+ * admit / finish times in seconds of a monotonic host clock, and the steps it
+ * has taken.  Any pointer may be NULL. */
+elmrt_status elmrt_server_job(elmrt_server* s, int64_t job_id, int32_t* state, double times[3],
+                              int64_t* steps_done);
+
+/* Copy out the final rho[N], u[D][N] and sums[4] of a finished job (as
+ * elmrt_read_macros; ELMRT_E_UNSTABLE if its flag was set, outputs still
+ * written).  ELMRT_E_STATE while the job is queued or resident.  The result
+ * is released after the call. */
+elmrt_status elmrt_server_result(elmrt_server* s, int64_t job_id, double* rho, double* u, double* sums);
+
+/* Lattice updates (cells x steps) advanced so far and the pool's free bytes. */
+elmrt_status elmrt_server_stats(elmrt_server* s, int64_t* lattice_updates, size_t* pool_free);
+
+/* Release every resident simulation and the server (not the pool).  NULL is
+ * ignored. */
+void elmrt_server_destroy(elmrt_server* s);
+
 /* Message of the last failed call on this thread ("" if none). */
 const char* elmrt_last_error(void);
 

@@ -6,7 +6,7 @@ import os
 import subprocess
 
 HERE = os.path.dirname(os.path.abspath(__file__))
-SOURCES = [os.path.join(HERE, "csrc", "elmrt_kernels.hip"), os.path.join(HERE, "csrc", "elmrt_api.cpp")]
+SOURCES = [os.path.join(HERE, "csrc", f) for f in ("elmrt_kernels.hip", "elmrt_api.cpp", "elmrt_server.cpp")]
 OUT = os.path.join(HERE, "libelmrt.so")
 
 HIPCC_FLAGS = [

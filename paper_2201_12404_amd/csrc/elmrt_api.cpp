@@ -25,6 +25,12 @@ elmrt_status fail(elmrt_status st, const std::string& msg)
     return st;
 }
 
+}  // namespace
+
+void elmrt::set_last_error(const std::string& msg) { g_last_error = msg; }
+
+namespace {
+
 elmrt_status hip_fail(hipError_t e, const char* what)
 {
     return fail(ELMRT_E_DEVICE, std::string(what) + ": " + hipGetErrorString(e));

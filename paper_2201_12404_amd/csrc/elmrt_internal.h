@@ -3,6 +3,8 @@
 #pragma once
 
 #include <hip/hip_runtime.h>
+
+#include <string>
 #include <stdint.h>
 
 namespace elmrt {
@@ -73,6 +75,9 @@ hipError_t launch_readout(const Launch& L, const void* cur, void* rho, void* u, 
 
 // f_i(r, t) = pulled populations, written to out[i*N + cell].
 hipError_t launch_pull(const Launch& L, const void* cur, void* out);
+
+// Message returned by elmrt_last_error on this thread.
+void set_last_error(const std::string& msg);
 
 // Tile shapes compiled for the collision kernel.
 bool collide_shape_supported(int D, int tx, int ty);

@@ -1,0 +1,343 @@
+// elmrt_server.cpp -- a request loop over the C ABI of elmrt.h: jobs (problem
+// statement, initial fields, step count) are queued, admitted in arrival
+// order while their workspace fits a caller-owned device pool, kept resident,
+// and advanced together in rounds: every round the resident jobs of each
+// lattice form one batch (elmrt_batch_*) that advances by the chunk or by the
+// fewest steps any member still needs, so that jobs finish exactly; finished
+// jobs are read out and their memory returns to the pool, after which queued
+// jobs are admitted.  Built on the public entry points only.
+#include "../../include/elmrt.h"
+#include "elmrt_internal.h"
+
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <chrono>
+#include <cstdint>
+#include <deque>
+#include <map>
+#include <memory>
+#include <string>
+#include <vector>
+
+namespace {
+
+double now_s()
+{
+    using namespace std::chrono;
+    return duration<double>(steady_clock::now().time_since_epoch()).count();
+}
+
+elmrt_status sfail(elmrt_status st, const std::string& msg)
+{
+    elmrt::set_last_error(msg);
+    return st;
+}
+
+// Lowest-address first-fit allocator over [0, size), 256-byte granules.
+class Pool {
+public:
+    explicit Pool(size_t size) { free_[0] = size; }
+    bool alloc(size_t bytes, size_t* off)
+    {
+        bytes = (bytes + 255) / 256 * 256;
+        for (auto it = free_.begin(); it != free_.end(); ++it) {
+            if (it->second < bytes) continue;
+            *off = it->first;
+            const size_t rest = it->second - bytes;
+            const size_t at = it->first + bytes;
+            free_.erase(it);
+            if (rest) free_[at] = rest;
+            used_[*off] = bytes;
+            return true;
+        }
+        return false;
+    }
+    void release(size_t off)
+    {
+        auto u = used_.find(off);
+        if (u == used_.end()) return;
+        size_t start = off, len = u->second;
+        used_.erase(u);
+        auto nx = free_.lower_bound(start);
+        if (nx != free_.end() && nx->first == start + len) {
+            len += nx->second;
+            nx = free_.erase(nx);
+        }
+        if (nx != free_.begin()) {
+            auto pv = std::prev(nx);
+            if (pv->first + pv->second == start) {
+                start = pv->first;
+                len += pv->second;
+                free_.erase(pv);
+            }
+        }
+        free_[start] = len;
+    }
+    size_t free_bytes() const
+    {
+        size_t s = 0;
+        for (auto& kv : free_) s += kv.second;
+        return s;
+    }
+
+private:
+    std::map<size_t, size_t> free_, used_;
+};
+
+enum JobState { QUEUED = 0, RESIDENT = 1, DONE = 2, FAILED = 3 };
+
+struct Job {
+    int64_t id = 0;
+    elmrt_params p{};
+    int D = 2;
+    size_t N = 0;
+    std::vector<double> rho0, u0;      // host inputs until admission
+    int64_t steps = 0, done = 0;
+    size_t off = 0, bytes = 0;
+    elmrt_sim* sim = nullptr;
+    JobState state = QUEUED;
+    double t_submit = 0, t_admit = 0, t_finish = 0;
+    std::vector<double> rho, u;        // results
+    double sums[4] = {0, 0, 0, 0};
+    elmrt_status status = ELMRT_OK;
+};
+
+struct Group {                          // resident jobs of one (lattice, precision)
+    elmrt_batch* batch = nullptr;
+    std::vector<Job*> members;
+    size_t off = 0;
+    bool has_table = false;
+};
+
+}  // namespace
+
+struct elmrt_server {
+    char* pool_base = nullptr;
+    std::unique_ptr<Pool> pool;
+    hipStream_t stream = nullptr;
+    int64_t chunk = 100;
+    int64_t next_id = 1;
+    std::deque<Job*> queue;
+    std::vector<Job*> resident;
+    std::map<int64_t, std::unique_ptr<Job>> jobs;
+    Group groups[4];                    // index 2 * lattice + precision
+    int64_t lattice_updates = 0;        // cells x steps advanced
+
+    ~elmrt_server()
+    {
+        for (auto& g : groups)
+            if (g.batch) elmrt_batch_destroy(g.batch);
+        for (auto& kv : jobs)
+            if (kv.second->sim) elmrt_destroy(kv.second->sim);
+    }
+};
+
+namespace {
+
+elmrt_status admit(elmrt_server* s)
+{
+    while (!s->queue.empty()) {
+        Job* j = s->queue.front();
+        size_t off = 0;
+        if (!s->pool->alloc(j->bytes, &off)) break;   // arrival order: wait for memory
+        s->queue.pop_front();
+        j->off = off;
+        elmrt_status st = elmrt_create(&j->p, s->pool_base + off, j->bytes, s->stream, &j->sim);
+        if (st == ELMRT_OK) st = elmrt_init_fields(j->sim, j->rho0.data(), j->u0.data());
+        j->rho0.clear();
+        j->rho0.shrink_to_fit();
+        j->u0.clear();
+        j->u0.shrink_to_fit();
+        j->t_admit = now_s();
+        if (st != ELMRT_OK) {
+            j->status = st;
+            j->state = FAILED;
+            j->t_finish = j->t_admit;
+            if (j->sim) elmrt_destroy(j->sim);
+            j->sim = nullptr;
+            s->pool->release(off);
+            continue;
+        }
+        j->state = RESIDENT;
+        s->resident.push_back(j);
+    }
+    return ELMRT_OK;
+}
+
+elmrt_status retire(elmrt_server* s, Job* j)
+{
+    j->rho.assign(j->N, 0.0);
+    j->u.assign((size_t)j->D * j->N, 0.0);
+    const elmrt_status st = elmrt_read_macros(j->sim, j->rho.data(), j->u.data(), j->sums);
+    j->status = st;
+    j->state = (st == ELMRT_OK || st == ELMRT_E_UNSTABLE) ? DONE : FAILED;
+    j->t_finish = now_s();
+    elmrt_destroy(j->sim);
+    j->sim = nullptr;
+    s->pool->release(j->off);
+    return ELMRT_OK;
+}
+
+// Make group g's batch match its members (rebuilt when the set changed).
+elmrt_status sync_batch(elmrt_server* s, Group& g, const std::vector<Job*>& members)
+{
+    if (g.batch && members == g.members) return ELMRT_OK;
+    if (g.batch) elmrt_batch_destroy(g.batch);
+    g.batch = nullptr;
+    if (g.has_table) s->pool->release(g.off);
+    g.has_table = false;
+    g.members = members;
+    if (members.empty()) return ELMRT_OK;
+    size_t bytes = 0;
+    elmrt_status st = elmrt_batch_workspace_bytes((int32_t)members.size(), &bytes);
+    if (st != ELMRT_OK) return st;
+    if (!s->pool->alloc(bytes, &g.off)) return sfail(ELMRT_E_NOMEM, "pool has no room for a batch table");
+    g.has_table = true;
+    std::vector<elmrt_sim*> sims;
+    for (Job* j : members) sims.push_back(j->sim);
+    return elmrt_batch_create(sims.data(), (int32_t)sims.size(), s->pool_base + g.off, bytes, &g.batch);
+}
+
+elmrt_status round_once(elmrt_server* s)
+{
+    elmrt_status st = admit(s);
+    if (st != ELMRT_OK) return st;
+    for (int gi = 0; gi < 4; ++gi) {
+        std::vector<Job*> members;
+        for (Job* j : s->resident)
+            if (2 * j->p.lattice + j->p.precision == gi) members.push_back(j);
+        st = sync_batch(s, s->groups[gi], members);
+        if (st != ELMRT_OK) return st;
+        if (members.empty()) continue;
+        int64_t n = s->chunk;
+        for (Job* j : members) n = std::min(n, j->steps - j->done);
+        if (n > 0) {
+            st = elmrt_batch_step(s->groups[gi].batch, n);
+            if (st != ELMRT_OK) return st;
+            for (Job* j : members) {
+                j->done += n;
+                s->lattice_updates += (int64_t)j->N * n;
+            }
+        }
+    }
+    // retire finished jobs (reads synchronise the stream)
+    std::vector<Job*> keep;
+    for (Job* j : s->resident) {
+        if (j->done >= j->steps) {
+            st = retire(s, j);
+            if (st != ELMRT_OK) return st;
+        } else {
+            keep.push_back(j);
+        }
+    }
+    s->resident.swap(keep);
+    return ELMRT_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+elmrt_status elmrt_server_create(void* dev_pool, size_t pool_bytes, void* stream, int64_t chunk_steps,
+                                 elmrt_server** out)
+{
+    if (!out) return sfail(ELMRT_E_INVALID, "out is NULL");
+    *out = nullptr;
+    if (!dev_pool || ((uintptr_t)dev_pool % 256) != 0) return sfail(ELMRT_E_INVALID, "pool is NULL or not 256-byte aligned");
+    if (pool_bytes < 4096) return sfail(ELMRT_E_INVALID, "pool too small");
+    if (chunk_steps < 1) return sfail(ELMRT_E_INVALID, "chunk_steps must be >= 1");
+    elmrt_server* s = new elmrt_server;
+    s->pool_base = (char*)dev_pool;
+    s->pool.reset(new Pool(pool_bytes));
+    s->stream = (hipStream_t)stream;
+    s->chunk = chunk_steps;
+    *out = s;
+    return ELMRT_OK;
+}
+
+elmrt_status elmrt_server_submit(elmrt_server* s, const elmrt_params* p, const double* rho0, const double* u0,
+                                 int64_t steps, int64_t* job_id)
+{
+    if (!s) return sfail(ELMRT_E_INVALID, "server is NULL");
+    if (!p || !rho0 || !u0) return sfail(ELMRT_E_INVALID, "params or fields are NULL");
+    if (steps < 0) return sfail(ELMRT_E_INVALID, "steps < 0");
+    size_t bytes = 0;
+    elmrt_status st = elmrt_workspace_bytes(p, &bytes);
+    if (st != ELMRT_OK) return sfail(st, std::string("job rejected: ") + elmrt_last_error());
+    auto j = std::make_unique<Job>();
+    j->id = s->next_id++;
+    j->p = *p;
+    j->D = p->lattice == ELMRT_D2Q9 ? 2 : 3;
+    j->N = (size_t)(p->n[0] * p->n[1] * p->n[2]);
+    j->rho0.assign(rho0, rho0 + j->N);
+    j->u0.assign(u0, u0 + (size_t)j->D * j->N);
+    j->steps = steps;
+    j->bytes = bytes;
+    j->t_submit = now_s();
+    if (job_id) *job_id = j->id;
+    s->queue.push_back(j.get());
+    s->jobs[j->id] = std::move(j);
+    return ELMRT_OK;
+}
+
+elmrt_status elmrt_server_run(elmrt_server* s, int32_t rounds, int32_t* queued, int32_t* resident)
+{
+    if (!s) return sfail(ELMRT_E_INVALID, "server is NULL");
+    for (int32_t r = 0; r < rounds; ++r) {
+        if (s->queue.empty() && s->resident.empty()) break;
+        elmrt_status st = round_once(s);
+        if (st != ELMRT_OK) return st;
+    }
+    if (queued) *queued = (int32_t)s->queue.size();
+    if (resident) *resident = (int32_t)s->resident.size();
+    return ELMRT_OK;
+}
+
+elmrt_status elmrt_server_job(elmrt_server* s, int64_t job_id, int32_t* state, double times[3], int64_t* steps_done)
+{
+    if (!s) return sfail(ELMRT_E_INVALID, "server is NULL");
+    auto it = s->jobs.find(job_id);
+    if (it == s->jobs.end()) return sfail(ELMRT_E_INVALID, "unknown job");
+    const Job* j = it->second.get();
+    if (state) *state = (int32_t)j->state;
+    if (times) {
+        times[0] = j->t_submit;
+        times[1] = j->t_admit;
+        times[2] = j->t_finish;
+    }
+    if (steps_done) *steps_done = j->done;
+    return ELMRT_OK;
+}
+
+elmrt_status elmrt_server_result(elmrt_server* s, int64_t job_id, double* rho, double* u, double* sums)
+{
+    if (!s) return sfail(ELMRT_E_INVALID, "server is NULL");
+    auto it = s->jobs.find(job_id);
+    if (it == s->jobs.end()) return sfail(ELMRT_E_INVALID, "unknown job");
+    Job* j = it->second.get();
+    if (j->state == QUEUED || j->state == RESIDENT) return sfail(ELMRT_E_STATE, "job not finished");
+    if (j->state == FAILED && j->rho.empty()) return sfail(j->status, "job failed");
+    if (rho) std::copy(j->rho.begin(), j->rho.end(), rho);
+    if (u) std::copy(j->u.begin(), j->u.end(), u);
+    if (sums) std::copy(j->sums, j->sums + 4, sums);
+    const elmrt_status st = j->status;
+    // results are handed over once
+    j->rho.clear();
+    j->rho.shrink_to_fit();
+    j->u.clear();
+    j->u.shrink_to_fit();
+    return st == ELMRT_E_UNSTABLE ? sfail(st, "job became unstable") : st;
+}
+
+elmrt_status elmrt_server_stats(elmrt_server* s, int64_t* lattice_updates, size_t* pool_free)
+{
+    if (!s) return sfail(ELMRT_E_INVALID, "server is NULL");
+    if (lattice_updates) *lattice_updates = s->lattice_updates;
+    if (pool_free) *pool_free = s->pool->free_bytes();
+    return ELMRT_OK;
+}
+
+void elmrt_server_destroy(elmrt_server* s) { delete s; }
+
+}  // extern "C"

@@ -73,6 +73,18 @@ _SIGS = {
     "elmrt_batch_autotune": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_int32, ctypes.POINTER(ctypes.c_int64)]),
     "elmrt_batch_destroy": (None, [ctypes.c_void_p]),
     "elmrt_destroy": (None, [ctypes.c_void_p]),
+    "elmrt_server_create": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_size_t, ctypes.c_void_p, ctypes.c_int64,
+                                           ctypes.POINTER(ctypes.c_void_p)]),
+    "elmrt_server_submit": (ctypes.c_int, [ctypes.c_void_p, ctypes.POINTER(elmrt_params), _dp, _dp, ctypes.c_int64,
+                                           ctypes.POINTER(ctypes.c_int64)]),
+    "elmrt_server_run": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_int32, ctypes.POINTER(ctypes.c_int32),
+                                        ctypes.POINTER(ctypes.c_int32)]),
+    "elmrt_server_job": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_int64, ctypes.POINTER(ctypes.c_int32), _dp,
+                                        ctypes.POINTER(ctypes.c_int64)]),
+    "elmrt_server_result": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_int64, _dp, _dp, _dp]),
+    "elmrt_server_stats": (ctypes.c_int, [ctypes.c_void_p, ctypes.POINTER(ctypes.c_int64),
+                                          ctypes.POINTER(ctypes.c_size_t)]),
+    "elmrt_server_destroy": (None, [ctypes.c_void_p]),
     "elmrt_last_error": (ctypes.c_char_p, []),
 }
 
@@ -277,6 +289,57 @@ def elmrt_destroy(sim: int) -> None:
     lib().elmrt_destroy(ctypes.c_void_p(sim))
 
 
+def elmrt_server_create(pool_ptr: int, pool_bytes: int, stream_ptr: int, chunk_steps: int) -> int:
+    h = ctypes.c_void_p()
+    _check(lib().elmrt_server_create(ctypes.c_void_p(pool_ptr), pool_bytes, ctypes.c_void_p(stream_ptr),
+                                     int(chunk_steps), ctypes.byref(h)))
+    return h.value
+
+
+def elmrt_server_submit(server: int, p: Params, rho0: np.ndarray, u0: np.ndarray, steps: int) -> int:
+    cp = p.c()
+    rho0 = np.ascontiguousarray(rho0, dtype=np.float64).reshape(-1)
+    u0 = np.ascontiguousarray(u0, dtype=np.float64).reshape(-1)
+    jid = ctypes.c_int64()
+    _check(lib().elmrt_server_submit(ctypes.c_void_p(server), ctypes.byref(cp), _dptr(rho0), _dptr(u0), int(steps),
+                                     ctypes.byref(jid)))
+    return jid.value
+
+
+def elmrt_server_run(server: int, rounds: int):
+    q, r = ctypes.c_int32(), ctypes.c_int32()
+    _check(lib().elmrt_server_run(ctypes.c_void_p(server), int(rounds), ctypes.byref(q), ctypes.byref(r)))
+    return q.value, r.value
+
+
+def elmrt_server_job(server: int, job_id: int):
+    st, done = ctypes.c_int32(), ctypes.c_int64()
+    t = np.zeros(3)
+    _check(lib().elmrt_server_job(ctypes.c_void_p(server), int(job_id), ctypes.byref(st), _dptr(t), ctypes.byref(done)))
+    return st.value, t, done.value
+
+
+def elmrt_server_result(server: int, job_id: int, N: int, D: int):
+    rho, u, sums = np.zeros(N), np.zeros((D, N)), np.zeros(4)
+    st = lib().elmrt_server_result(ctypes.c_void_p(server), int(job_id), _dptr(rho), _dptr(u), _dptr(sums))
+    if st == ELMRT_E_UNSTABLE:
+        err = ElmrtUnstable(st, lib().elmrt_last_error().decode())
+        err.rho, err.u, err.sums = rho, u, sums
+        raise err
+    _check(st)
+    return rho, u, sums
+
+
+def elmrt_server_stats(server: int):
+    lu, free = ctypes.c_int64(), ctypes.c_size_t()
+    _check(lib().elmrt_server_stats(ctypes.c_void_p(server), ctypes.byref(lu), ctypes.byref(free)))
+    return lu.value, free.value
+
+
+def elmrt_server_destroy(server: int) -> None:
+    lib().elmrt_server_destroy(ctypes.c_void_p(server))
+
+
 def elmrt_last_error() -> str:
     return lib().elmrt_last_error().decode()
 
@@ -366,6 +429,53 @@ class Batch:
     def close(self):
         if self.handle:
             elmrt_batch_destroy(self.handle)
+            self.handle = 0
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+class Server:
+    """Request loop over a torch-allocated device pool on torch's current
+    stream (see elmrt_server_* in include/elmrt.h)."""
+
+    QUEUED, RESIDENT, DONE, FAILED = 0, 1, 2, 3
+
+    def __init__(self, pool_bytes: int, chunk_steps: int = 100, device: str = "cuda:0"):
+        import torch
+
+        lib()
+        raw = torch.empty(pool_bytes + 256, dtype=torch.uint8, device=torch.device(device))
+        off = (-raw.data_ptr()) % 256
+        self.pool = raw[off: off + pool_bytes]
+        self.stream = torch.cuda.current_stream(torch.device(device))
+        self.handle = elmrt_server_create(self.pool.data_ptr(), pool_bytes, self.stream.cuda_stream, chunk_steps)
+        self.shapes = {}
+
+    def submit(self, p: Params, rho0, u0, steps: int) -> int:
+        jid = elmrt_server_submit(self.handle, p, rho0, u0, steps)
+        self.shapes[jid] = (p.N, p.D)
+        return jid
+
+    def run(self, rounds: int = 1):
+        return elmrt_server_run(self.handle, rounds)
+
+    def job(self, jid: int):
+        return elmrt_server_job(self.handle, jid)
+
+    def result(self, jid: int):
+        N, D = self.shapes[jid]
+        return elmrt_server_result(self.handle, jid, N, D)
+
+    def stats(self):
+        return elmrt_server_stats(self.handle)
+
+    def close(self):
+        if self.handle:
+            elmrt_server_destroy(self.handle)
             self.handle = 0
 
     def __del__(self):

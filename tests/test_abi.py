@@ -139,3 +139,10 @@ def test_plane_block_limit():
     p = E.Params(lattice=1, n=(5000, 5000, 4), precision=1, bc=(0, 0, 1))
     with pytest.raises(E.ElmrtError, match="plane block"):
         E.elmrt_workspace_bytes(p)
+
+
+def test_server_create_rejects_bad_arguments_without_a_device():
+    with pytest.raises(E.ElmrtError, match="aligned"):
+        E.elmrt_server_create(0, 1 << 20, 0, 10)
+    with pytest.raises(E.ElmrtError, match="chunk"):
+        E.elmrt_server_create(256, 1 << 20, 0, 0)
