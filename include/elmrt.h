@@ -116,6 +116,13 @@ elmrt_status elmrt_step_timed(elmrt_sim* s, int64_t nsteps, double ms[2]);
  * filled) once a non-finite or non-positive density has been seen. */
 elmrt_status elmrt_read_macros(elmrt_sim* s, double* rho, double* u, double* sums);
 
+/* Fluid velocity u + F dt/(2 rho) of the exact-difference forcing (Sec. 2.3,
+ * F on the read-out density) at time t, u[D][N] FP64 host.  In a resting
+ * two-phase state the bare velocity of elmrt_read_macros equals -F/(2 rho)
+ * near interfaces; this is the velocity whose maximum measures spurious
+ * currents (Sec. 3.1.2).  Same errors as elmrt_read_macros. */
+elmrt_status elmrt_read_fluid_velocity(elmrt_sim* s, double* u);
+
 /* Read the populations f_i(r, t) (post-streaming) into host FP64 f[i*N + cell]. */
 elmrt_status elmrt_read_populations(elmrt_sim* s, double* f);
 

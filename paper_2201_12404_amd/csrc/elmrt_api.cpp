@@ -378,7 +378,7 @@ elmrt_status elmrt_step_timed(elmrt_sim* s, int64_t nsteps, double ms[2])
     return st;
 }
 
-elmrt_status elmrt_read_macros(elmrt_sim* s, double* rho, double* u, double* sums)
+static elmrt_status read_impl(elmrt_sim* s, double* rho, double* u, double* sums, bool fluid)
 {
     if (!s) return fail(ELMRT_E_INVALID, "sim is NULL");
     if (!s->initialised) return fail(ELMRT_E_STATE, "elmrt_init_fields has not been called");
@@ -387,6 +387,8 @@ elmrt_status elmrt_read_macros(elmrt_sim* s, double* rho, double* u, double* sum
     void* tu = tmp + s->N * s->es;
     hipError_t e = elmrt::launch_readout(s->L, s->buf[s->cur], trho, tu, s->partials, kReadBlocks, s->flag);
     if (e != hipSuccess) return hip_fail(e, "readout kernel");
+    if (fluid && (e = elmrt::launch_fluid_velocity(s->L, trho, tu, s->ph)) != hipSuccess)
+        return hip_fail(e, "velocity shift kernel");
     std::vector<char> h((1 + (size_t)s->D) * s->N * s->es);
     std::vector<double> part((size_t)kReadBlocks * 4);
     unsigned flag = 0;
@@ -418,6 +420,17 @@ elmrt_status elmrt_read_macros(elmrt_sim* s, double* rho, double* u, double* sum
     }
     if (flag) return fail(ELMRT_E_UNSTABLE, "non-finite or non-positive density encountered");
     return ELMRT_OK;
+}
+
+elmrt_status elmrt_read_macros(elmrt_sim* s, double* rho, double* u, double* sums)
+{
+    return read_impl(s, rho, u, sums, false);
+}
+
+elmrt_status elmrt_read_fluid_velocity(elmrt_sim* s, double* u)
+{
+    if (!u) return fail(ELMRT_E_INVALID, "u is NULL");
+    return read_impl(s, nullptr, u, nullptr, true);
 }
 
 elmrt_status elmrt_read_populations(elmrt_sim* s, double* f)

@@ -65,6 +65,10 @@ hipError_t launch_collide(const Launch& L, int tx, int ty, int tm, const void* c
 // u0 -= F(rho0) / (2 rho0) in place (fluid velocity -> bare velocity).
 hipError_t launch_shift_velocity(const Launch& L, const double* rho0, double* u0, const Phys<double>& ph);
 
+// u += F(rho) / (2 rho) in place on working-precision arrays (bare velocity ->
+// fluid velocity).
+hipError_t launch_fluid_velocity(const Launch& L, const void* rho, void* u, const Phys<double>& ph);
+
 // f := f^eq(rho0, u0) stored so that pull-streaming yields f^eq at every cell.
 hipError_t launch_init(const Launch& L, const double* rho0, const double* u0, void* cur);
 

@@ -978,14 +978,15 @@ __global__ __launch_bounds__(TX* TY) __attribute__((amdgpu_waves_per_eu(CollideW
                                (const T*)J.rho, (const T*)J.q, J.g, J.ph, J.cbx, J.cby, J.ctm);
 }
 
-// Initial velocity shift: the fluid velocity of the exact-difference forcing
-// is u + F dt/(2 rho), so starting from a prescribed fluid velocity u0 needs
-// the bare velocity u0 - F(rho0)/(2 rho0) in f^eq.  F is the force of
-// Sec. 2.3 evaluated on the initial density (FP64, neighbours fetched from
-// global memory).  Overwrites u (staged u0) in place; rho is only read.
-template <int D>
-__global__ __launch_bounds__(256) void k_shift_velocity(const double* __restrict__ rho, double* __restrict__ u,
-                                                        Grid g, FlatGrid fg, Phys<double> ph)
+// Velocity shift between the bare velocity u = sum c f / rho and the fluid
+// velocity u + F dt/(2 rho) of the exact-difference forcing: u += sign F/(2 rho)
+// in place, F the force of Sec. 2.3 on the density field (FP64, neighbours
+// fetched from global memory).  sign = -1 turns a prescribed initial fluid
+// velocity into the bare velocity of f^eq; sign = +1 turns a read-out bare
+// velocity into the fluid velocity.  rho is only read.
+template <int D, typename T>
+__global__ __launch_bounds__(256) void k_shift_velocity(const T* __restrict__ rho, T* __restrict__ u, Grid g,
+                                                        FlatGrid fg, Phys<double> ph, double sign)
 {
     constexpr int Q = Lat<D>::Q;
     const uint32_t cell = blockIdx.x * 256u + threadIdx.x;
@@ -997,9 +998,9 @@ __global__ __launch_bounds__(256) void k_shift_velocity(const double* __restrict
         const int x = map_coord(co[0] + dx, g.n[0], g.wall[0], &flip);
         const int y = (D >= 2) ? map_coord(co[1] + dy, g.n[1], g.wall[1], &flip) : 0;
         const int z = (D == 3) ? map_coord(co[2] + dz, g.n[2], g.wall[2], &flip) : 0;
-        return rho[x + g.n[0] * y + g.nxny * z];
+        return (double)rho[x + g.n[0] * y + g.nxny * z];
     };
-    const double r0 = rho[cell];
+    const double r0 = (double)rho[cell];
     const double psi0 = psi_signed<double>(r0, ph);
     double G[3] = {0.0, 0.0, 0.0}, K[3] = {0.0, 0.0, 0.0};
 #pragma unroll
@@ -1023,7 +1024,8 @@ __global__ __launch_bounds__(256) void k_shift_velocity(const double* __restrict
 #pragma unroll
     for (int a = 0; a < D; ++a) {
         const double F = 2.0 * psi0 * G[a] + ph.kappa * r0 * K[a];
-        u[(size_t)a * g.N + cell] -= F / (2.0 * r0);
+        T& ua = u[(size_t)a * g.N + cell];
+        ua = (T)((double)ua + sign * F / (2.0 * r0));
     }
 }
 
@@ -1286,9 +1288,24 @@ hipError_t launch_shift_velocity(const Launch& L, const double* rho0, double* u0
     const FlatGrid fg = flat_of(L.g);
     const dim3 grid(flat_blocks(L.g)), block(256);
     if (L.D == 2)
-        hipLaunchKernelGGL((k_shift_velocity<2>), grid, block, 0, L.stream, rho0, u0, L.g, fg, ph);
+        hipLaunchKernelGGL((k_shift_velocity<2, double>), grid, block, 0, L.stream, rho0, u0, L.g, fg, ph, -1.0);
     else
-        hipLaunchKernelGGL((k_shift_velocity<3>), grid, block, 0, L.stream, rho0, u0, L.g, fg, ph);
+        hipLaunchKernelGGL((k_shift_velocity<3, double>), grid, block, 0, L.stream, rho0, u0, L.g, fg, ph, -1.0);
+    return hipGetLastError();
+}
+
+hipError_t launch_fluid_velocity(const Launch& L, const void* rho, void* u, const Phys<double>& ph)
+{
+    const FlatGrid fg = flat_of(L.g);
+    const dim3 grid(flat_blocks(L.g)), block(256);
+    if (L.D == 2 && !L.fp64)
+        hipLaunchKernelGGL((k_shift_velocity<2, float>), grid, block, 0, L.stream, (const float*)rho, (float*)u, L.g, fg, ph, 1.0);
+    else if (L.D == 2)
+        hipLaunchKernelGGL((k_shift_velocity<2, double>), grid, block, 0, L.stream, (const double*)rho, (double*)u, L.g, fg, ph, 1.0);
+    else if (!L.fp64)
+        hipLaunchKernelGGL((k_shift_velocity<3, float>), grid, block, 0, L.stream, (const float*)rho, (float*)u, L.g, fg, ph, 1.0);
+    else
+        hipLaunchKernelGGL((k_shift_velocity<3, double>), grid, block, 0, L.stream, (const double*)rho, (double*)u, L.g, fg, ph, 1.0);
     return hipGetLastError();
 }
 

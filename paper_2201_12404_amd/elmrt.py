@@ -61,6 +61,7 @@ _SIGS = {
     "elmrt_step_timed": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_int64, _dp]),
     "elmrt_read_macros": (ctypes.c_int, [ctypes.c_void_p, _dp, _dp, _dp]),
     "elmrt_read_populations": (ctypes.c_int, [ctypes.c_void_p, _dp]),
+    "elmrt_read_fluid_velocity": (ctypes.c_int, [ctypes.c_void_p, _dp]),
     "elmrt_velocities": (ctypes.c_int32, [ctypes.c_int32, ctypes.POINTER(ctypes.c_int32)]),
     "elmrt_coexistence": (ctypes.c_int, [ctypes.POINTER(elmrt_params), _dp, _dp, _dp]),
     "elmrt_set_tiling": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_int32, ctypes.c_int32, ctypes.c_int32]),
@@ -220,6 +221,17 @@ def elmrt_read_macros(sim: int, N: int, D: int):
         raise err
     _check(st)
     return rho, u, sums
+
+
+def elmrt_read_fluid_velocity(sim: int, N: int, D: int) -> np.ndarray:
+    u = np.zeros((D, N))
+    st = lib().elmrt_read_fluid_velocity(ctypes.c_void_p(sim), _dptr(u))
+    if st == ELMRT_E_UNSTABLE:
+        err = ElmrtUnstable(st, lib().elmrt_last_error().decode())
+        err.u = u
+        raise err
+    _check(st)
+    return u
 
 
 def elmrt_read_populations(sim: int, Q: int, N: int) -> np.ndarray:
@@ -382,6 +394,9 @@ class Simulation:
 
     def read_populations(self):
         return elmrt_read_populations(self.handle, self.params.Q, self.params.N)
+
+    def read_fluid_velocity(self):
+        return elmrt_read_fluid_velocity(self.handle, self.params.N, self.params.D)
 
     def set_tiling(self, tx, ty, tm):
         elmrt_set_tiling(self.handle, tx, ty, tm)

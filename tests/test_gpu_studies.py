@@ -1,0 +1,86 @@
+"""The BGK-vs-entropic study harness (paper_2201_12404_amd/studies.py): the
+fluid-velocity readout it rests on against the oracle, and the paper's
+qualitative findings at reduced size (printed, with the bars below)."""
+import os
+import sys
+
+import numpy as np
+import pytest
+
+from common import oracle_params, rel_max
+from oracle import oracle as O
+from paper_2201_12404_amd import elmrt as E
+from paper_2201_12404_amd import studies as S
+from paper_2201_12404_amd import workloads as W
+
+pytestmark = pytest.mark.gpu
+
+
+def say(*a):
+    print(*a, flush=True)
+    sys.stdout.flush()
+
+
+@pytest.fixture(scope="module", autouse=True)
+def _gpu():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    torch.cuda.set_device(0)
+    O.set_threads(min(16, os.cpu_count() or 1))
+    yield
+
+
+@pytest.mark.parametrize("collision", [E.ELMRT_ENTROPIC, E.ELMRT_BGK])
+def test_fluid_velocity_matches_oracle(collision):
+    """u + F/(2 rho) of a resting drop (FP64, 64^2, 150 steps) against the
+    oracle's bare velocity plus its force field: 1e-12."""
+    w = S.drop(0.8, 0.05, N=64, R=16.0, precision=1)
+    sim = E.Simulation(E.params_for(w, collision))
+    sim.init_fields(*W.initial_fields(w))
+    sim.step(150)
+    uf_g = sim.read_fluid_velocity()
+    sim.close()
+    p = oracle_params(w, collision)
+    f = O.init_fluid(p, *W.initial_fields(w))
+    O.step(p, f, 150)
+    rho_o, u_o, _ = O.macros(p, f)
+    uf_o = u_o + O.force_field(p, rho_o) / (2.0 * rho_o)
+    e = rel_max(uf_g, uf_o)
+    say(f"fluid velocity vs oracle ({'BGK' if collision else 'entropic'}): {e:.3e}, max|u| {np.abs(uf_o).max():.3e}")
+    assert e < 1e-10
+
+
+def test_spurious_currents_bgk_vs_entropic():
+    """Resting drops at T/Tc = 0.5925 for nu = 0.1 .. 0.005 (128^2, R = 25,
+    FP32, 3000 steps).  Paper (Sec. 3.1.2): at nu = 0.1 the two collisions give
+    nearly the same spurious currents; at lower viscosities the entropic one
+    reduces them, up to twofold.  Bars: ratio entropic / BGK within [0.7, 1.3]
+    at nu = 0.1, and <= 1.05 at the lowest nu both survive."""
+    nus = [0.1, 0.03, 0.01, 0.005]
+    runs, rate = S.spurious_currents([0.592454], nus, steps=3000)
+    table = {}
+    for r in runs:
+        table[(r.collision, r.workload.nu_liquid)] = r.umax if r.stable else None
+    for nu in nus:
+        say(f"nu={nu}: BGK {table[(E.ELMRT_BGK, nu)]}  entropic {table[(E.ELMRT_ENTROPIC, nu)]}")
+    say(f"batched study rate {rate / 1e6:.0f} MLUPS")
+    b, e = table[(E.ELMRT_BGK, 0.1)], table[(E.ELMRT_ENTROPIC, 0.1)]
+    assert b and e and 0.7 <= e / b <= 1.3
+    both = [nu for nu in nus if table[(E.ELMRT_BGK, nu)] and table[(E.ELMRT_ENTROPIC, nu)]]
+    lo = min(both)
+    assert table[(E.ELMRT_ENTROPIC, lo)] <= 1.05 * table[(E.ELMRT_BGK, lo)]
+    # the entropic collision survives at least as far down in viscosity
+    assert all(table[(E.ELMRT_ENTROPIC, nu)] for nu in both)
+
+
+def test_spurious_current_temperature_exponent():
+    """max spurious current ~ (1 - T/Tc)^m over T/Tc = 0.60 .. 0.80 at
+    nu = 0.1 (entropic).  The paper reports m ~ 2.2; printed, and the bar is
+    only that the fit is a clear power law with 1 < m < 4."""
+    temps = [0.6, 0.65, 0.7, 0.75, 0.8]
+    runs, _ = S.spurious_currents(temps, [0.1], collisions=(E.ELMRT_ENTROPIC,), steps=3000)
+    u = [r.umax for r in runs]
+    m, c = S.fit_power(temps, u)
+    say(f"spurious currents {dict(zip(temps, u))}; fit m = {m:.2f}, C = {c:.3e}")
+    assert all(np.isfinite(u)) and 1.0 < m < 4.0
