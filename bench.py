@@ -135,13 +135,16 @@ def batched_vs_plain(steps: int = 2000, trial_steps: int = 4):
             "accuracy": "bitwise equal to the plain path (same kernels)"}
 
 
-def served_vs_plain(count: int, step_scale: float, pool_gib: float = 16.0, chunk: int = 200):
+def served_vs_plain(count: int, step_scale: float, pool_gib: float = 16.0, chunk: int = 200,
+                    fill: int = 4 << 20, policy: int = 1):
     """The served impact stream (seeded Poisson arrivals, 20 jobs/s, D2Q9 and
     D3Q27 drop impacts of mixed size, density ratio and speed), first 'count'
     jobs with step counts scaled by 'step_scale'.  Served: arrivals replayed
     in real time into the request loop (admission by footprint into a
     'pool_gib' GiB pool, resident jobs advanced in shared batches of 'chunk'
-    steps).  Plain: each job alone through the single-simulation path; its
+    steps, least remaining work first up to 'fill' cells per round).  Plain:
+    each job
+    alone through the single-simulation path; its
     FIFO latencies follow from the measured service times and the same
     arrival times.  Latency = arrival to completion."""
     import numpy as np
@@ -175,6 +178,8 @@ def served_vs_plain(count: int, step_scale: float, pool_gib: float = 16.0, chunk
     # served: real-time replay of the arrivals
     inputs = [W.initial_fields(w) for _, w, _ in jobs]
     srv = E.Server(pool_bytes=int(pool_gib * (1 << 30)), chunk_steps=chunk)
+    srv.set_fill(fill)
+    srv.set_policy(policy)
     ids = [None] * len(jobs)
     t_start = time.monotonic()
     k = 0

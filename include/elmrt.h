@@ -200,12 +200,17 @@ void elmrt_destroy(elmrt_sim* s);
  * admitted in arrival order while their workspace fits a caller-owned device
  * pool (first fit; a job that does not fit waits, and so do the ones behind
  * it).  Admitted jobs stay resident and are advanced in rounds by
- * elmrt_server_run: in every round the resident jobs of each lattice and
- * precision form one batch (the elmrt_batch_* entry points) that advances by
- * chunk_steps, or by the fewest steps any member still needs, so every job
- * stops exactly at its step count; finished jobs are read out (fields and
- * sums kept on the host until elmrt_server_result) and their memory goes back
- * to the pool before the next admission.  A job's result is bitwise the same
+ * elmrt_server_run: in every round the resident jobs first in the scheduling
+ * order (elmrt_server_set_policy: least remaining work, cells x steps, first
+ * -- the default -- or arrival order), until their cells reach a fill budget
+ * (elmrt_server_set_fill, default 2^22 cells, at least one job), form one
+ * batch per lattice and precision (the elmrt_batch_* entry points) that
+ * advances by chunk_steps, or by the fewest steps any of them still needs,
+ * so every job stops exactly at its step count; small jobs share rounds,
+ * large ones take turns.
+ * Finished jobs are read out (fields and sums kept on the host until
+ * elmrt_server_result) and their memory goes back to the pool before the
+ * next admission.  A job's result is bitwise the same
  * as the same simulation run alone.  The server owns its job records; the
  * pool and the stream are the caller's and must outlive it.  Not thread-safe:
  * one thread drives a server. */
@@ -215,6 +220,13 @@ typedef struct elmrt_server elmrt_server;
  * job workspaces and batch tables from; stream: hipStream_t or NULL. */
 elmrt_status elmrt_server_create(void* dev_pool, size_t pool_bytes, void* stream, int64_t chunk_steps,
                                  elmrt_server** out);
+
+/* Cells a round advances at most (beyond the first job); >= 1. */
+elmrt_status elmrt_server_set_fill(elmrt_server* s, int64_t cells);
+
+/* Scheduling order of resident jobs: 0 arrival, 1 least remaining work
+ * (cells x remaining steps) first. */
+elmrt_status elmrt_server_set_policy(elmrt_server* s, int32_t policy);
 
 /* Queue a job; the fields (rho0[N], u0[D][N], FP64 host) are copied.  Fails
  * with ELMRT_E_INVALID when elmrt_create would reject p.  *job_id > 0. */

@@ -1,11 +1,13 @@
 // elmrt_server.cpp -- a request loop over the C ABI of elmrt.h: jobs (problem
 // statement, initial fields, step count) are queued, admitted in arrival
 // order while their workspace fits a caller-owned device pool, kept resident,
-// and advanced together in rounds: every round the resident jobs of each
-// lattice form one batch (elmrt_batch_*) that advances by the chunk or by the
-// fewest steps any member still needs, so that jobs finish exactly; finished
-// jobs are read out and their memory returns to the pool, after which queued
-// jobs are admitted.  Built on the public entry points only.
+// and advanced together in rounds: every round the resident jobs first in
+// policy order (arrival, or least remaining work), up to a budget of cells
+// that occupies the device, form one batch per lattice and
+// precision (elmrt_batch_*) that advances by the chunk or by the fewest steps
+// any member still needs, so that jobs finish exactly; finished jobs are read
+// out and their memory returns to the pool, after which queued jobs are
+// admitted.  Built on the public entry points only.
 #include "../../include/elmrt.h"
 #include "elmrt_internal.h"
 
@@ -117,6 +119,8 @@ struct elmrt_server {
     std::unique_ptr<Pool> pool;
     hipStream_t stream = nullptr;
     int64_t chunk = 100;
+    int64_t fill = 4 << 20;             // cells advanced per round (at least one job)
+    int32_t policy = 1;                 // 0 arrival order, 1 shortest remaining work first
     int64_t next_id = 1;
     std::deque<Job*> queue;
     std::vector<Job*> resident;
@@ -203,9 +207,25 @@ elmrt_status round_once(elmrt_server* s)
 {
     elmrt_status st = admit(s);
     if (st != ELMRT_OK) return st;
+    // This round advances resident jobs, in policy order (arrival, or least
+    // remaining work -- cells x steps -- first), until their cells reach the
+    // fill budget: enough work to occupy the device, while the others wait
+    // their turn instead of slowing every running one down.
+    std::vector<Job*> order = s->resident;
+    if (s->policy == 1)
+        std::stable_sort(order.begin(), order.end(), [](const Job* a, const Job* b) {
+            return (double)a->N * (double)(a->steps - a->done) < (double)b->N * (double)(b->steps - b->done);
+        });
+    std::vector<Job*> running;
+    int64_t cells = 0;
+    for (Job* j : order) {
+        if (!running.empty() && cells >= s->fill) break;
+        running.push_back(j);
+        cells += (int64_t)j->N;
+    }
     for (int gi = 0; gi < 4; ++gi) {
         std::vector<Job*> members;
-        for (Job* j : s->resident)
+        for (Job* j : running)
             if (2 * j->p.lattice + j->p.precision == gi) members.push_back(j);
         st = sync_batch(s, s->groups[gi], members);
         if (st != ELMRT_OK) return st;
@@ -232,6 +252,11 @@ elmrt_status round_once(elmrt_server* s)
         }
     }
     s->resident.swap(keep);
+    if (s->resident.empty())   // release the last batches and their tables
+        for (auto& g : s->groups) {
+            st = sync_batch(s, g, {});
+            if (st != ELMRT_OK) return st;
+        }
     return ELMRT_OK;
 }
 
@@ -253,6 +278,22 @@ elmrt_status elmrt_server_create(void* dev_pool, size_t pool_bytes, void* stream
     s->stream = (hipStream_t)stream;
     s->chunk = chunk_steps;
     *out = s;
+    return ELMRT_OK;
+}
+
+elmrt_status elmrt_server_set_fill(elmrt_server* s, int64_t cells)
+{
+    if (!s) return sfail(ELMRT_E_INVALID, "server is NULL");
+    if (cells < 1) return sfail(ELMRT_E_INVALID, "fill must be >= 1 cell");
+    s->fill = cells;
+    return ELMRT_OK;
+}
+
+elmrt_status elmrt_server_set_policy(elmrt_server* s, int32_t policy)
+{
+    if (!s) return sfail(ELMRT_E_INVALID, "server is NULL");
+    if (policy != 0 && policy != 1) return sfail(ELMRT_E_INVALID, "policy must be 0 or 1");
+    s->policy = policy;
     return ELMRT_OK;
 }
 

@@ -76,6 +76,8 @@ _SIGS = {
     "elmrt_destroy": (None, [ctypes.c_void_p]),
     "elmrt_server_create": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_size_t, ctypes.c_void_p, ctypes.c_int64,
                                            ctypes.POINTER(ctypes.c_void_p)]),
+    "elmrt_server_set_fill": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_int64]),
+    "elmrt_server_set_policy": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_int32]),
     "elmrt_server_submit": (ctypes.c_int, [ctypes.c_void_p, ctypes.POINTER(elmrt_params), _dp, _dp, ctypes.c_int64,
                                            ctypes.POINTER(ctypes.c_int64)]),
     "elmrt_server_run": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_int32, ctypes.POINTER(ctypes.c_int32),
@@ -308,6 +310,14 @@ def elmrt_server_create(pool_ptr: int, pool_bytes: int, stream_ptr: int, chunk_s
     return h.value
 
 
+def elmrt_server_set_fill(server: int, cells: int) -> None:
+    _check(lib().elmrt_server_set_fill(ctypes.c_void_p(server), int(cells)))
+
+
+def elmrt_server_set_policy(server: int, policy: int) -> None:
+    _check(lib().elmrt_server_set_policy(ctypes.c_void_p(server), int(policy)))
+
+
 def elmrt_server_submit(server: int, p: Params, rho0: np.ndarray, u0: np.ndarray, steps: int) -> int:
     cp = p.c()
     rho0 = np.ascontiguousarray(rho0, dtype=np.float64).reshape(-1)
@@ -469,6 +479,12 @@ class Server:
         self.stream = torch.cuda.current_stream(torch.device(device))
         self.handle = elmrt_server_create(self.pool.data_ptr(), pool_bytes, self.stream.cuda_stream, chunk_steps)
         self.shapes = {}
+
+    def set_fill(self, cells: int):
+        elmrt_server_set_fill(self.handle, cells)
+
+    def set_policy(self, policy: int):
+        elmrt_server_set_policy(self.handle, policy)
 
     def submit(self, p: Params, rho0, u0, steps: int) -> int:
         jid = elmrt_server_submit(self.handle, p, rho0, u0, steps)

@@ -102,3 +102,27 @@ def test_server_rejects_invalid_job():
     with pytest.raises(E.ElmrtError, match="rejected"):
         srv.submit(p, np.zeros(48), np.zeros(96), 10)
     srv.close()
+
+
+@pytest.mark.parametrize("policy", [0, 1])
+def test_fill_budget_takes_turns(policy):
+    """With a fill budget of one cell only one resident job advances in a
+    round: the oldest (policy 0) or the one with the least remaining work,
+    cells x steps (policy 1); the other starts when it is done, and both
+    results are those of the jobs run alone."""
+    w1, w2 = W.impact_job(2, 128, 1000, 0.05, 12, 0), W.impact_job(2, 96, 10, 0.03, 8, 1)
+    srv = E.Server(pool_bytes=1 << 28, chunk_steps=4)
+    srv.set_fill(1)
+    srv.set_policy(policy)
+    a = srv.submit(E.params_for(w1), *W.initial_fields(w1), 12)
+    b = srv.submit(E.params_for(w2), *W.initial_fields(w2), 8)
+    srv.run(1)
+    first, second = (a, b) if policy == 0 else (b, a)
+    assert srv.job(first)[2] == 4 and srv.job(second)[2] == 0
+    while srv.run(1) != (0, 0):
+        pass
+    for jid, w, steps in ((a, w1, 12), (b, w2, 8)):
+        rho_s, u_s, _ = srv.result(jid)
+        rho_a, u_a, _ = alone(w, steps)
+        assert np.array_equal(rho_s, rho_a) and np.array_equal(u_s, u_a)
+    srv.close()
