@@ -134,6 +134,10 @@ int32_t elmrt_velocities(int32_t lattice, int32_t* c);
 elmrt_status elmrt_coexistence(const elmrt_params* p, double* rho_vapour, double* rho_liquid,
                                double* p_sat);
 
+/* Peng-Robinson pressure P(rho) (Sec. 3.1) of the EOS in p at its T/Tc, for
+ * n host FP64 densities (post-processing: Laplace pressure jumps). */
+elmrt_status elmrt_pressure(const elmrt_params* p, const double* rho, double* P, int64_t n);
+
 /* Tile shape of the collision kernel: tx x ty cells per workgroup, marched
  * over tm (>= 1) planes along the last axis.  Compiled shapes:
  * D2Q9 ty = 1 with tx = 64, 128 or 256; D3Q27 (tx, ty) = (64, 4), (64, 2),

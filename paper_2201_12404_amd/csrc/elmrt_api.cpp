@@ -473,6 +473,17 @@ elmrt_status elmrt_coexistence(const elmrt_params* p, double* rho_vapour, double
     return ELMRT_OK;
 }
 
+elmrt_status elmrt_pressure(const elmrt_params* p, const double* rho, double* P, int64_t n)
+{
+    if (!p || (n > 0 && (!rho || !P))) return fail(ELMRT_E_INVALID, "NULL argument");
+    if (n < 0) return fail(ELMRT_E_INVALID, "n < 0");
+    if (!(p->eos_a > 0) || !(p->eos_b > 0) || !(p->eos_R > 0)) return fail(ELMRT_E_INVALID, "EOS a, b, R must be > 0");
+    if (!(p->T_over_Tc > 0)) return fail(ELMRT_E_INVALID, "T/Tc must be > 0");
+    PengRobinson pr(p->eos_a, p->eos_b, p->eos_R, p->acentric, p->T_over_Tc);
+    for (int64_t k = 0; k < n; ++k) P[k] = pr.P(rho[k]);
+    return ELMRT_OK;
+}
+
 elmrt_status elmrt_set_tiling(elmrt_sim* s, int32_t tx, int32_t ty, int32_t tm)
 {
     if (!s) return fail(ELMRT_E_INVALID, "sim is NULL");

@@ -64,6 +64,7 @@ _SIGS = {
     "elmrt_read_fluid_velocity": (ctypes.c_int, [ctypes.c_void_p, _dp]),
     "elmrt_velocities": (ctypes.c_int32, [ctypes.c_int32, ctypes.POINTER(ctypes.c_int32)]),
     "elmrt_coexistence": (ctypes.c_int, [ctypes.POINTER(elmrt_params), _dp, _dp, _dp]),
+    "elmrt_pressure": (ctypes.c_int, [ctypes.POINTER(elmrt_params), _dp, _dp, ctypes.c_int64]),
     "elmrt_set_tiling": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_int32, ctypes.c_int32, ctypes.c_int32]),
     "elmrt_autotune": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_int32, ctypes.POINTER(ctypes.c_int64)]),
     "elmrt_batch_workspace_bytes": (ctypes.c_int, [ctypes.c_int32, ctypes.POINTER(ctypes.c_size_t)]),
@@ -255,6 +256,14 @@ def elmrt_coexistence(p: Params):
     rv, rl, ps = ctypes.c_double(), ctypes.c_double(), ctypes.c_double()
     _check(lib().elmrt_coexistence(ctypes.byref(cp), ctypes.byref(rv), ctypes.byref(rl), ctypes.byref(ps)))
     return rv.value, rl.value, ps.value
+
+
+def elmrt_pressure(p: Params, rho: np.ndarray) -> np.ndarray:
+    cp = p.c()
+    rho = np.ascontiguousarray(rho, dtype=np.float64).reshape(-1)
+    P = np.zeros_like(rho)
+    _check(lib().elmrt_pressure(ctypes.byref(cp), _dptr(rho), _dptr(P), rho.size))
+    return P
 
 
 def elmrt_set_tiling(sim: int, tx: int, ty: int, tm: int) -> None:

@@ -119,3 +119,113 @@ def fit_power(temps, umax):
     y = np.log(np.asarray(umax, dtype=np.float64))
     m, logc = np.polyfit(x, y, 1)
     return float(m), float(np.exp(logc))
+
+
+# ------------------------------------------ thermodynamic consistency (f2)
+
+
+def _eos(a: float) -> dict:
+    return dict(eos_a=a, eos_b=0.095, eos_R=1.0, acentric=0.344)
+
+
+def _coex(tr: float, a: float):
+    p = E.Params(lattice=0, n=(8, 8, 1), T_over_Tc=tr, **_eos(a))
+    rv, rl, _ = E.elmrt_coexistence(p)
+    return rv, rl
+
+
+def kappa_for(tr: float, a: float) -> float:
+    """kappa~ for an interface width of ~5: the EOS-set-B value scaled by
+    a / 0.003 (at fixed T/Tc and b the pressure scales with a)."""
+    return W.kappa_w5(tr) * a / 0.003
+
+
+def slab(tr: float, a: float = 0.003, n=(800, 10), half: float = 200.0, width: float = 5.0, nu: float = 0.1,
+         precision: int = 0) -> W.Workload:
+    """Flat-interface case of Sec. 3.1.1: a liquid column 2*half wide at the
+    centre of a periodic n[0] x n[1] box of vapour (Maxwell densities)."""
+    rv, rl = _coex(tr, a)
+    return W.Workload(name=f"slab-{tr}-{a}", lattice=0, n=tuple(n), bc=(0, 0), precision=precision, eos=_eos(a),
+                      T_over_Tc=tr, kappa_tilde=kappa_for(tr, a), nu_liquid=nu, nu_vapour=nu, rho_v=rv, rho_l=rl,
+                      kind="slab", radius=half, width=width, centre=((n[0] - 1) / 2, (n[1] - 1) / 2))
+
+
+def laplace_drop(tr: float, R: float, a: float = 0.003, width: float = 5.0, nu: float = 0.1,
+                 precision: int = 0) -> W.Workload:
+    """Resting drop of radius R in a periodic square box of side 4R + 20W."""
+    rv, rl = _coex(tr, a)
+    N = int(4 * R + 20 * width)
+    return W.Workload(name=f"laplace-{tr}-{R}-{a}", lattice=0, n=(N, N), bc=(0, 0), precision=precision, eos=_eos(a),
+                      T_over_Tc=tr, kappa_tilde=kappa_for(tr, a), nu_liquid=nu, nu_vapour=nu, rho_v=rv, rho_l=rl,
+                      kind="drop", radius=R, width=width, centre=((N - 1) / 2, (N - 1) / 2))
+
+
+def _converge(workloads, steps_max: int, chunk: int, tol: float):
+    """Advance the workloads together until every density field changes by
+    less than tol * max(rho) (max norm) over a chunk, or steps_max; returns
+    the final density fields, the steps taken and whether each converged."""
+    sims = []
+    for w in workloads:
+        sim = E.Simulation(E.params_for(w))
+        sim.init_fields(*W.initial_fields(w))
+        sims.append(sim)
+    b = E.Batch(sims)
+    prev = [None] * len(sims)
+    conv = [False] * len(sims)
+    done = 0
+    while done < steps_max and not all(conv):
+        b.step(chunk)
+        done += chunk
+        for k, sim in enumerate(sims):
+            rho, _, _ = sim.read_macros()
+            if prev[k] is not None and np.abs(rho - prev[k]).max() < tol * np.abs(rho).max():
+                conv[k] = True
+            prev[k] = rho
+    b.close()
+    for sim in sims:
+        sim.close()
+    return prev, done, conv
+
+
+def coexistence_sweep(temps, a: float = 0.003, steps_max: int = 40000, chunk: int = 2000, tol: float = 1e-9,
+                      **kw):
+    """Converged flat interfaces at each T/Tc: simulated vapour and liquid
+    densities (means over the bulk of each phase), the Maxwell values and the
+    interface thickness W = (rho_l - rho_v) / max |d rho / dx| (Sec. 3.1.1)."""
+    ws = [slab(tr, a, **kw) for tr in temps]
+    fields, steps, conv = _converge(ws, steps_max, chunk, tol)
+    out = []
+    for w, rho, ok in zip(ws, fields, conv):
+        nx, ny = w.n
+        prof = rho.reshape(ny, nx).mean(axis=0)
+        x = np.arange(nx)
+        x1, x2 = w.centre[0] - w.radius, w.centre[0] + w.radius
+        liquid = np.abs(x - w.centre[0]) < w.radius - 10 * w.width
+        vapour = (x < x1 - 10 * w.width) | (x > x2 + 10 * w.width)
+        rl, rv = float(prof[liquid].mean()), float(prof[vapour].mean())
+        grad = np.abs(np.roll(prof, -1) - np.roll(prof, 1)) / 2.0
+        out.append(dict(T_over_Tc=w.T_over_Tc, a=a, rho_l=rl, rho_v=rv, rho_l_maxwell=w.rho_l,
+                        rho_v_maxwell=w.rho_v, W=float((rl - rv) / grad.max()), steps=steps, converged=ok))
+    return out
+
+
+def laplace_sweep(temps, radii, a: float = 0.003, steps_max: int = 40000, chunk: int = 2000, tol: float = 1e-9,
+                  **kw):
+    """Converged resting drops: pressure jump dP = P(rho_in) - P(rho_out)
+    between the drop centre and the box corner, the equimolar radius R_e
+    (pi R_e^2 (rho_in - rho_out) = sum (rho - rho_out), D = 2) and the
+    surface tension sigma = dP R_e of the Laplace law (Sec. 3.1.2)."""
+    ws = [laplace_drop(tr, R, a, **kw) for tr in temps for R in radii]
+    fields, steps, conv = _converge(ws, steps_max, chunk, tol)
+    out = []
+    for w, rho, ok in zip(ws, fields, conv):
+        N = w.n[0]
+        f2 = rho.reshape(N, N)
+        c = N // 2
+        r_in, r_out = float(f2[c - 2:c + 3, c - 2:c + 3].mean()), float(f2[:3, :3].mean())
+        P = E.elmrt_pressure(E.params_for(w), np.array([r_in, r_out]))
+        dP = float(P[0] - P[1])
+        Re = float(np.sqrt((rho - r_out).sum() / (np.pi * (r_in - r_out))))
+        out.append(dict(T_over_Tc=w.T_over_Tc, a=a, R0=w.radius, rho_in=r_in, rho_out=r_out, dP=dP, R_e=Re,
+                        sigma=dP * Re, steps=steps, converged=ok))
+    return out

@@ -22,6 +22,8 @@ Shared definitions (lattice units, node coordinates 0..n-1):
   drop indicator    : phi_d = (1 - tanh(2 (|r - c| - R)/W)) / 2
   film indicator    : phi_f = (1 - tanh(2 (z - h)/W)) / 2, z = wall-normal
                       coordinate, first fluid node at 0, wall plane at -1/2
+  slab indicator    : phi_s = (tanh(2 (x - x1)/W) - tanh(2 (x - x2)/W)) / 2,
+                      liquid between x1 and x2
 """
 from __future__ import annotations
 
@@ -105,7 +107,7 @@ class Workload:
     nu_vapour: float
     rho_v: float
     rho_l: float
-    kind: str               # "drop" or "impact"
+    kind: str               # "drop", "impact" or "slab"
     radius: float
     width: float = 5.0
     film: float = 0.0       # film thickness h (impact)
@@ -144,6 +146,13 @@ def initial_fields(w: Workload):
     phi_d = 0.5 * (1.0 - np.tanh(2.0 * (r - w.radius) / w.width))
     if w.kind == "drop":
         rho0 = w.rho_v + (w.rho_l - w.rho_v) * phi_d
+        u0 = np.zeros((D, w.N))
+    elif w.kind == "slab":
+        # liquid column of half-width 'radius' centred at centre[0] along x
+        x = X[0]
+        phi_s = 0.5 * (np.tanh(2.0 * (x - (w.centre[0] - w.radius)) / w.width)
+                       - np.tanh(2.0 * (x - (w.centre[0] + w.radius)) / w.width))
+        rho0 = w.rho_v + (w.rho_l - w.rho_v) * phi_s
         u0 = np.zeros((D, w.N))
     elif w.kind == "impact":
         zn = X[D - 1]                                   # wall-normal coordinate

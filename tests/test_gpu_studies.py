@@ -84,3 +84,37 @@ def test_spurious_current_temperature_exponent():
     m, c = S.fit_power(temps, u)
     say(f"spurious currents {dict(zip(temps, u))}; fit m = {m:.2f}, C = {c:.3e}")
     assert all(np.isfinite(u)) and 1.0 < m < 4.0
+
+
+def test_coexistence_matches_maxwell():
+    """Flat interfaces (800 x 10, liquid column 400 wide, a = 0.003,
+    b = 0.095, FP32) converged to 1e-9 in the max norm: the liquid density
+    within 0.5% of the Maxwell construction at every temperature (Sec.
+    3.1.1); vapour densities and interface thickness printed."""
+    temps = [0.6, 0.7, 0.8, 0.9]
+    res = S.coexistence_sweep(temps, steps_max=30000)
+    for r in res:
+        say(f"T/Tc={r['T_over_Tc']}: rho_l {r['rho_l']:.5f} (Maxwell {r['rho_l_maxwell']:.5f})  "
+            f"rho_v {r['rho_v']:.5f} (Maxwell {r['rho_v_maxwell']:.5f})  W {r['W']:.2f}  "
+            f"steps {r['steps']} converged {r['converged']}")
+        assert abs(r["rho_l"] / r["rho_l_maxwell"] - 1) < 5e-3
+
+
+def test_laplace_law_and_surface_tension_scaling():
+    """Resting drops R0 = 25, 40, 60 at T/Tc = 0.8 (a = 0.003): dP > 0 and
+    dP R_e constant within 5% (Laplace law, D = 2).  Surface tension over
+    T/Tc = 0.85, 0.9, 0.95 (R0 = 40): the fitted exponent of (1 - T/Tc),
+    3/2 in the mean-field limit near Tc (Sec. 3.1.2), printed with the bar
+    1.2 .. 1.8."""
+    res = S.laplace_sweep([0.8], [25.0, 40.0, 60.0], steps_max=30000)
+    sig = [r["sigma"] for r in res]
+    for r in res:
+        say(f"R0={r['R0']}: dP {r['dP']:.4e} R_e {r['R_e']:.2f} sigma {r['sigma']:.4e} steps {r['steps']}")
+    assert all(r["dP"] > 0 for r in res)
+    assert max(sig) / min(sig) - 1 < 0.05
+    temps = [0.85, 0.9, 0.95]
+    res = S.laplace_sweep(temps, [40.0], steps_max=30000)
+    s = [r["sigma"] for r in res]
+    m, c = S.fit_power(temps, s)
+    say(f"sigma(T/Tc) {dict(zip(temps, s))}; exponent {m:.3f}")
+    assert 1.2 < m < 1.8
