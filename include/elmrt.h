@@ -139,14 +139,17 @@ elmrt_status elmrt_coexistence(const elmrt_params* p, double* rho_vapour, double
 elmrt_status elmrt_pressure(const elmrt_params* p, const double* rho, double* P, int64_t n);
 
 /* Tile shape of the collision kernel: tx x ty cells per workgroup, marched
- * over tm (>= 1) planes along the last axis.  Compiled shapes:
+ * over tm planes along the last axis.  Compiled shapes:
  * D2Q9 ty = 1 with tx = 64, 128 or 256; D3Q27 (tx, ty) = (64, 4), (64, 2),
- * (32, 8) or (128, 2).  Other shapes return ELMRT_E_INVALID and leave the
- * tiling unchanged.  Every shape gives bitwise the same result. */
+ * (32, 8) or (128, 2).  Other shapes, or tm < 0, return ELMRT_E_INVALID and
+ * leave the tiling unchanged.  tm = 0 (the default, with 64 x 1 or 64 x 4)
+ * picks the depth automatically: 16 inside a batch, and for a sim stepped
+ * alone the deepest of 16, 8, 4, 2, 1 whose launch still has >= 2048 (D3Q27)
+ * or 4096 (D2Q9) wavefronts.  Every tiling gives bitwise the same result. */
 elmrt_status elmrt_set_tiling(elmrt_sim* s, int32_t tx, int32_t ty, int32_t tm);
 
 /* Pick the collision tiling of s by measurement: every compiled tile shape
- * of the lattice with marching depths 4..64 is run for 1 + trial_steps steps
+ * of the lattice with marching depths 1..64 is run for 1 + trial_steps steps
  * (the extra step untimed) and timed with HIP events on the sim's stream;
  * the fastest is kept.  The trial steps advance the simulation (results do
  * not depend on the tiling); their number is written to *steps_taken (may be

@@ -264,7 +264,7 @@ elmrt_status elmrt_create(const elmrt_params* p, void* ws, size_t ws_bytes, void
     s->initialised = false;
     s->tx = 64;
     s->ty = s->D == 3 ? 4 : 1;
-    s->tm = 16;
+    s->tm = 0;   // automatic marching depth (collide_depth)
     // physics constants (host FP64; cast to the working precision at launch)
     PengRobinson pr(p->eos_a, p->eos_b, p->eos_R, p->acentric, p->T_over_Tc);
     s->ph.RT = pr.RT;
@@ -326,6 +326,26 @@ elmrt_status elmrt_init_fields(elmrt_sim* s, const double* rho0, const double* u
     return ELMRT_OK;
 }
 
+// Marching depth of the collision tiles.  An explicit depth is used as set.
+// The automatic depth is 16 planes inside a batch (whose launch has work to
+// spare) and, for a grid launched alone, the deepest of 16, 8, 4, 2, 1 that
+// still gives min_waves wavefronts: on small grids a deep march leaves compute
+// units idle, a shallow one recomputes psi on the 4 halo planes of every tile.
+// The thresholds are measured (64^3..256^3 and 128^2..1024^2 impacts): about
+// two thirds of the wavefronts the chip holds at each kernel's occupancy (3
+// per SIMD for D3Q27 FP32, 5 for D2Q9).
+static int collide_depth(const elmrt_sim* s, bool batched)
+{
+    if (s->tm > 0) return s->tm;
+    int tm = std::min(16, s->L.g.n[s->D - 1]);
+    if (batched) return tm;
+    const long long min_waves = s->D == 3 ? 2048 : 4096;
+    const long long waves_per_block = (s->tx * s->ty + 63) / 64;
+    while (tm > 1 && elmrt::collide_tiling(s->D, s->L.g, s->tx, s->ty, tm).blocks * waves_per_block < min_waves)
+        tm /= 2;
+    return tm;
+}
+
 // Enqueue nsteps steps.  With ev != NULL (2*nsteps + 1 events) an event is
 // recorded before the first kernel and after every kernel, so that kernel k
 // of the run lies between ev[k] and ev[k+1].
@@ -342,7 +362,7 @@ static elmrt_status step_impl(elmrt_sim* s, int64_t nsteps, hipEvent_t* ev)
         e = elmrt::launch_macro(s->L, cur, s->rho, s->q, s->flag);
         if (e != hipSuccess) return hip_fail(e, "moment kernel");
         if (ev && (e = hipEventRecord(ev[2 * k + 1], s->stream)) != hipSuccess) return hip_fail(e, "hipEventRecord");
-        e = elmrt::launch_collide(s->L, s->tx, s->ty, s->tm, cur, nxt, s->rho, s->q, s->ph);
+        e = elmrt::launch_collide(s->L, s->tx, s->ty, collide_depth(s, false), cur, nxt, s->rho, s->q, s->ph);
         if (e != hipSuccess) return hip_fail(e, "collision kernel");
         if (ev && (e = hipEventRecord(ev[2 * k + 2], s->stream)) != hipSuccess) return hip_fail(e, "hipEventRecord");
         s->cur = 1 - s->cur;
@@ -487,7 +507,7 @@ elmrt_status elmrt_pressure(const elmrt_params* p, const double* rho, double* P,
 elmrt_status elmrt_set_tiling(elmrt_sim* s, int32_t tx, int32_t ty, int32_t tm)
 {
     if (!s) return fail(ELMRT_E_INVALID, "sim is NULL");
-    if (tm < 1) return fail(ELMRT_E_INVALID, "tm must be >= 1");
+    if (tm < 0) return fail(ELMRT_E_INVALID, "tm must be >= 0 (0: automatic)");
     if (!elmrt::collide_shape_supported(s->D, tx, ty)) return fail(ELMRT_E_INVALID, "tile shape not compiled");
     s->tx = tx;
     s->ty = ty;
@@ -508,7 +528,7 @@ std::vector<std::array<int, 3>> tiling_candidates(int D)
     std::vector<std::array<int, 3>> c;
     const int shapes2[][2] = {{64, 1}, {128, 1}, {256, 1}};
     const int shapes3[][2] = {{64, 4}, {32, 8}, {64, 2}, {128, 2}};
-    const int tms[] = {4, 8, 16, 32, 64};
+    const int tms[] = {1, 2, 4, 8, 16, 32, 64};
     if (D == 2)
         for (auto& sh : shapes2)
             for (int tm : tms) c.push_back({sh[0], sh[1], tm});
@@ -643,14 +663,15 @@ elmrt_status batch_build(elmrt_batch* b)
         J.flag = s->flag;
         J.g = s->L.g;
         J.ph = s->ph;
-        const elmrt::Tiling mt = elmrt::macro_tiling(s->D, s->L.g);
-        const elmrt::Tiling ct = elmrt::collide_tiling(s->D, s->L.g, s->tx, s->ty, s->tm);
+        const elmrt::Tiling mt = elmrt::macro_tiling(s->D, s->L.g, false);
+        const int tm = collide_depth(s, true);
+        const elmrt::Tiling ct = elmrt::collide_tiling(s->D, s->L.g, s->tx, s->ty, tm);
         J.mbx = mt.bx;
         J.mby = mt.by;
-        J.mtm = elmrt::kMacroTM;
+        J.mtm = mt.tm;
         J.cbx = ct.bx;
         J.cby = ct.by;
-        J.ctm = s->tm;
+        J.ctm = tm;
         J.mfirst = (int)mfirst;
         J.cfirst = (int)cfirst;
         J.cur0 = s->cur;

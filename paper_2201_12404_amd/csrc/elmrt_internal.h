@@ -88,12 +88,14 @@ bool collide_shape_supported(int D, int tx, int ty);
 
 // Tiling arithmetic shared by the single and batched launches.
 struct Tiling {
-    int bx, by, bm;
+    int bx, by, bm, tm;   // tiles along x, y, the marching axis; planes per tile
     long long blocks;
 };
-Tiling macro_tiling(int D, const Grid& g);
+// alone: the launch covers one grid, so a small grid shortens the march to
+// spread its rows over more workgroups; batched launches keep the full march.
+Tiling macro_tiling(int D, const Grid& g, bool alone);
 Tiling collide_tiling(int D, const Grid& g, int tx, int ty, int tm);
-constexpr int kMacroTX = 256, kMacroTM = 8;
+constexpr int kMacroTX = 256;
 
 // Batched launches over a device job table (jobs sorted by first workgroup).
 // All jobs share the lattice, the precision and, for the collision, the tile

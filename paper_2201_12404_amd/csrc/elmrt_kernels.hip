@@ -1209,10 +1209,10 @@ hipError_t collide_batch_dispatch(int tx, int ty, const BatchJob* jobs, int njob
 template <int D, typename T>
 hipError_t macro_t(const Launch& L, const void* cur, void* rho, void* q, unsigned* flag)
 {
-    const Tiling t = macro_tiling(D, L.g);
+    const Tiling t = macro_tiling(D, L.g, true);
     if (t.blocks <= 0 || t.blocks > 0x7fffffffLL) return hipErrorInvalidConfiguration;
     hipLaunchKernelGGL((k_macro<D, T, kMacroTX, 1>), dim3((unsigned)t.blocks), dim3(kMacroTX, 1), 0, L.stream,
-                       (const T*)cur, (T*)rho, (T*)q, flag, L.g, t.bx, t.by, kMacroTM);
+                       (const T*)cur, (T*)rho, (T*)q, flag, L.g, t.bx, t.by, t.tm);
     return hipGetLastError();
 }
 
@@ -1236,13 +1236,20 @@ bool collide_shape_supported(int D, int tx, int ty)
 // The moment pass takes whole rows of up to 256 cells per workgroup: the
 // x-shifted pulls of a row then touch only the row's own cache lines (the
 // periodic wrap stays in the row), where 64-cell segments share a line with
-// the neighbouring segment at each end.
-Tiling macro_tiling(int D, const Grid& g)
+// the neighbouring segment at each end.  A tile marches over up to 8 planes;
+// the pass reuses nothing between planes, so a single grid too small to give
+// kMacroMinBlocks workgroups at 8 planes has its march shortened (down to one
+// plane) to spread the rows over more workgroups.
+constexpr int kMacroTM = 8;
+constexpr long long kMacroMinBlocks = 2048;
+Tiling macro_tiling(int D, const Grid& g, bool alone)
 {
     Tiling t;
     t.bx = (g.n[0] + kMacroTX - 1) / kMacroTX;
     t.by = (D == 3) ? g.n[1] : 1;
-    t.bm = (g.n[D - 1] + kMacroTM - 1) / kMacroTM;
+    t.tm = kMacroTM;
+    while (alone && t.tm > 1 && (long long)t.bx * t.by * ((g.n[D - 1] + t.tm - 1) / t.tm) < kMacroMinBlocks) t.tm /= 2;
+    t.bm = (g.n[D - 1] + t.tm - 1) / t.tm;
     t.blocks = (long long)t.bx * t.by * t.bm;
     return t;
 }
@@ -1252,6 +1259,7 @@ Tiling collide_tiling(int D, const Grid& g, int tx, int ty, int tm)
     Tiling t;
     t.bx = (g.n[0] + tx - 1) / tx;
     t.by = (D == 3) ? (g.n[1] + ty - 1) / ty : 1;
+    t.tm = tm;
     t.bm = (g.n[D - 1] + tm - 1) / tm;
     t.blocks = (long long)t.bx * t.by * t.bm;
     return t;

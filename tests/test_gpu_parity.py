@@ -190,10 +190,13 @@ def test_impact_3d_fp32_scaled():
     assert n["l2_u"] < 1e-4 and n["e_u"] < 1e-3
 
 
-@pytest.mark.parametrize("D,shapes", [(3, [(64, 4, 16), (32, 8, 5), (64, 2, 7), (128, 2, 64)]),
-                                      (2, [(64, 1, 16), (128, 1, 3), (256, 1, 100)])])
+@pytest.mark.parametrize("D,shapes", [(3, [(64, 4, 16), (32, 8, 5), (64, 2, 7), (128, 2, 64), (64, 4, 1),
+                                          (64, 4, 2), (64, 4, 0)]),
+                                      (2, [(64, 1, 16), (128, 1, 3), (256, 1, 100), (256, 1, 1), (64, 1, 2),
+                                           (64, 1, 0)])])
 def test_tile_shapes_bitwise_identical(D, shapes):
-    """Every tile shape and marching depth gives bitwise the same state."""
+    """Every tile shape and marching depth (0: automatic) gives bitwise the
+    same state."""
     w = _small(D, (0, 0, 1) if D == 3 else (0, 1), 0)
     ref = None
     for sh in shapes:
