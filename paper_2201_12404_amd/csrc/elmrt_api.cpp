@@ -409,10 +409,11 @@ static elmrt_status read_impl(elmrt_sim* s, double* rho, double* u, double* sums
     if (e != hipSuccess) return hip_fail(e, "readout kernel");
     if (fluid && (e = elmrt::launch_fluid_velocity(s->L, trho, tu, s->ph)) != hipSuccess)
         return hip_fail(e, "velocity shift kernel");
-    std::vector<char> h((1 + (size_t)s->D) * s->N * s->es);
+    // only the fields asked for cross PCIe (density first, then velocity)
+    std::vector<char> h(((u ? 1 + (size_t)s->D : (rho ? 1 : 0))) * s->N * s->es);
     std::vector<double> part((size_t)kReadBlocks * 4);
     unsigned flag = 0;
-    e = hipMemcpyAsync(h.data(), tmp, h.size(), hipMemcpyDeviceToHost, s->stream);
+    e = h.empty() ? hipSuccess : hipMemcpyAsync(h.data(), tmp, h.size(), hipMemcpyDeviceToHost, s->stream);
     if (e == hipSuccess) e = hipMemcpyAsync(part.data(), s->partials, part.size() * sizeof(double), hipMemcpyDeviceToHost, s->stream);
     if (e == hipSuccess) e = hipMemcpyAsync(&flag, s->flag, sizeof(unsigned), hipMemcpyDeviceToHost, s->stream);
     if (e == hipSuccess) e = hipStreamSynchronize(s->stream);

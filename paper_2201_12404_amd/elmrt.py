@@ -226,6 +226,19 @@ def elmrt_read_macros(sim: int, N: int, D: int):
     return rho, u, sums
 
 
+def elmrt_read_density(sim: int, N: int) -> np.ndarray:
+    """rho[N] alone (elmrt_read_macros with u and sums NULL: only the
+    density crosses to the host)."""
+    rho = np.zeros(N)
+    st = lib().elmrt_read_macros(ctypes.c_void_p(sim), _dptr(rho), None, None)
+    if st == ELMRT_E_UNSTABLE:
+        err = ElmrtUnstable(st, lib().elmrt_last_error().decode())
+        err.rho = rho
+        raise err
+    _check(st)
+    return rho
+
+
 def elmrt_read_fluid_velocity(sim: int, N: int, D: int) -> np.ndarray:
     u = np.zeros((D, N))
     st = lib().elmrt_read_fluid_velocity(ctypes.c_void_p(sim), _dptr(u))
@@ -410,6 +423,9 @@ class Simulation:
 
     def read_macros(self):
         return elmrt_read_macros(self.handle, self.params.N, self.params.D)
+
+    def read_density(self):
+        return elmrt_read_density(self.handle, self.params.N)
 
     def read_populations(self):
         return elmrt_read_populations(self.handle, self.params.Q, self.params.N)

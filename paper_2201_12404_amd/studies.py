@@ -5,7 +5,11 @@ many runs advance together in one batch):
 * spurious currents of 2-D resting drops against temperature and viscosity,
   with the (1 - T/Tc)^m fit (Sec. 3.1.2);
 * the stability domain of 2-D drop impacts over viscosity and impact speed
-  (Sec. 3.2).
+  (Sec. 3.2);
+* the thermodynamic-consistency sweeps: flat-interface coexistence and the
+  Laplace-law surface tension (Sec. 3.1);
+* the crown radius of drop impacts on a film against time, with its
+  square-root fit (Sec. 3.2; crown diameter in 3-D, Sec. 3.3).
 
 Spurious currents are the maximum of the fluid velocity u + F/(2 rho) (the
 bare velocity of a resting two-phase state is -F/(2 rho), not a current).
@@ -228,4 +232,183 @@ def laplace_sweep(temps, radii, a: float = 0.003, steps_max: int = 40000, chunk:
         Re = float(np.sqrt((rho - r_out).sum() / (np.pi * (r_in - r_out))))
         out.append(dict(T_over_Tc=w.T_over_Tc, a=a, R0=w.radius, rho_in=r_in, rho_out=r_out, dP=dP, R_e=Re,
                         sigma=dP * Re, steps=steps, converged=ok))
+    return out
+
+
+# --------------------------------------------------- crown radius (Sec. 3.2, 3.3)
+
+
+def surface_tension(tr: float, radii=(30.0, 45.0), a: float = 0.003, **kw) -> float:
+    """Surface tension of EOS set B (scaled by a) at T/Tc = tr from the
+    Laplace law on converged resting drops (mean over the radii)."""
+    return float(np.mean([r["sigma"] for r in laplace_sweep([tr], list(radii), a=a, **kw)]))
+
+
+def impact_case(R0: float, u0: float, nu_l: float, D: int = 2, ratio: int = 1000, nu_ratio: float = 15.0,
+                film: float | None = None, width: float = 5.0, extent=None, precision: int = 0) -> W.Workload:
+    """Drop impact on a film (Sec. 3.2, 3.3) with drop radius R0, impact
+    speed u0 and liquid kinematic viscosity nu_l (lattice units).
+
+    2-D (Sec. 3.2): a 24 R0 x 12 R0 box, film thickness h = R0.  3-D
+    (Sec. 3.3): a 14 R0 x 14 R0 x 6 R0 box, h = 0.44 R0.  Periodic side
+    walls, bounce-back walls normal to the last axis, the drop centred over
+    the axis with a gap of 2 W above the film, vapour/liquid kinematic
+    viscosity ratio nu_ratio (15 for air/water), density ratio 'ratio' by the
+    Maxwell table of EOS set B."""
+    tr = W.TR_OF_RATIO[ratio]
+    rv, rl = W.COEX_B_TABLE[tr]
+    if extent is None:
+        extent = (24.0, 12.0) if D == 2 else (14.0, 14.0, 6.0)
+    n = tuple(int(round(e * R0)) for e in extent)
+    h = (R0 if D == 2 else 0.44 * R0) if film is None else film
+    zc = h + R0 + 2.0 * width
+    centre = tuple((k - 1) / 2 for k in n[:-1]) + (zc,)
+    return W.Workload(name=f"impact-R{R0:g}-U{u0:g}-nu{nu_l:g}-d{D}", lattice=0 if D == 2 else 1, n=n,
+                      bc=(0,) * (D - 1) + (1,), precision=precision, eos=W.EOS_B, T_over_Tc=tr,
+                      kappa_tilde=W.kappa_w5(tr), nu_liquid=nu_l, nu_vapour=nu_ratio * nu_l, rho_v=rv, rho_l=rl,
+                      kind="impact", radius=R0, width=width, film=h, centre=centre, u_impact=u0)
+
+
+def impact_we_re(We: float, Re: float, R0: float, sigma: float, D: int = 2, **kw) -> W.Workload:
+    """impact_case at given Weber and Reynolds numbers
+    We = 2 rho_l R0 U0^2 / sigma and Re = 2 U0 R0 / nu_l (Sec. 3.2); sigma is
+    the surface tension of the EOS in lattice units (surface_tension)."""
+    tr = W.TR_OF_RATIO[kw.get("ratio", 1000)]
+    rl = W.COEX_B_TABLE[tr][1]
+    u0 = float(np.sqrt(We * sigma / (2.0 * rl * R0)))
+    return impact_case(R0, u0, 2.0 * u0 * R0 / Re, D=D, **kw)
+
+
+def weber(w: W.Workload, sigma: float) -> float:
+    return 2.0 * w.rho_l * w.radius * w.u_impact ** 2 / sigma
+
+
+def reynolds(w: W.Workload) -> float:
+    return 2.0 * w.u_impact * w.radius / w.nu_liquid
+
+
+def _ray_extent(line: np.ndarray, axis: int, step: int, mid: float) -> float:
+    """Distance from cell 'axis' along a line (direction step = +1 or -1, up
+    to half the line) to the outer edge of the first liquid run (values above
+    mid) met on the way: the crown wall, or the liquid column on the axis.
+    The edge is interpolated linearly between the last liquid and the first
+    vapour cell.  0 if the ray meets no liquid; half the line if the run
+    reaches that far."""
+    n = len(line)
+    half = n // 2
+    k = 0
+    while k <= half and line[(axis + step * k) % n] <= mid:
+        k += 1
+    if k > half:
+        return 0.0
+    while k < half:
+        a, b = line[(axis + step * k) % n], line[(axis + step * (k + 1)) % n]
+        if b <= mid:
+            return k + (a - mid) / (a - b)
+        k += 1
+    return n / 2.0
+
+
+def crown_radius(rho: np.ndarray, w: W.Workload, probe: float | None = None) -> float:
+    """Spreading (crown base) radius of an impact, in the plane one interface
+    width above the initial film surface (or 'probe' cells above it): the
+    distance from the impact axis to the outer edge of the first liquid met
+    going outward (density above the mean of the coexistence densities),
+    averaged over the rays along +x and -x (2-D) or +-x and +-y (3-D; the
+    crown diameter is twice this).  Cells are x fastest; the last axis is
+    wall-normal."""
+    n = w.n
+    mid = 0.5 * (w.rho_l + w.rho_v)
+    z = int(round(w.film + (w.width if probe is None else probe)))
+    f = np.asarray(rho).reshape(n[::-1])
+    xc = int(round(w.centre[0]))
+    if w.D == 2:
+        return 0.5 * (_ray_extent(f[z], xc, 1, mid) + _ray_extent(f[z], xc, -1, mid))
+    yc = int(round(w.centre[1]))
+    plane = f[z]                                   # (ny, nx)
+    rows = (plane[yc, :], plane[:, xc])
+    return 0.25 * sum(_ray_extent(line, c, d, mid) for line, c in zip(rows, (xc, yc)) for d in (1, -1))
+
+
+def crown_history(w: W.Workload, t_end: float = 1.0, samples: int = 20, collision: int = E.ELMRT_ENTROPIC,
+                  tiling=None, probes=(None,), progress=None) -> dict:
+    """Run an impact and sample the crown radius (one series per probe
+    height, crown_radius).  Time is counted from the geometric contact of the
+    drop with the film (gap / U0 steps after the start) in units of
+    tau = 2 R0 / U0 (Sec. 3.2), up to t_end tau.  progress(step, t_tau,
+    radii) is called after every sample when given."""
+    gap = w.centre[-1] - w.radius - w.film
+    tau = 2.0 * w.radius / w.u_impact
+    t0 = gap / w.u_impact
+    marks = sorted(set(int(round(t0 + tau * t_end * k / samples)) for k in range(1, samples + 1)))
+    sim = E.Simulation(E.params_for(w, collision))
+    try:
+        if tiling:
+            sim.set_tiling(*tiling)
+        sim.init_fields(*W.initial_fields(w))
+        done, t, r = 0, [], []
+        for m in marks:
+            sim.step(m - done)
+            done = m
+            rho = sim.read_density()
+            t.append((m - t0) / tau)
+            r.append([crown_radius(rho, w, p) / w.radius for p in probes])
+            if progress is not None:
+                progress(m, t[-1], r[-1])
+    finally:
+        sim.close()
+    r = np.array(r)
+    return dict(t_tau=np.array(t), r_R0=r[:, 0], r_probes=r, tau=tau, t0=t0, u0=w.u_impact, nu_l=w.nu_liquid,
+                Re=reynolds(w), steps=marks[-1])
+
+
+def fit_sqrt(t_tau: np.ndarray, r_R0: np.ndarray, lo: float = 0.05, hi: float = 0.5):
+    """Least-squares fit of log r = n log t + log c over lo <= t/tau <= hi:
+    returns the exponent n (1/2 for the square-root law of the early crown
+    spreading) and the prefactor c of r / R0 = c (t / tau)^n."""
+    sel = (t_tau >= lo) & (t_tau <= hi) & (r_R0 > 0)
+    if sel.sum() < 3:
+        raise ValueError("fewer than 3 samples with a crown in the fit window")
+    n, logc = np.polyfit(np.log(t_tau[sel]), np.log(r_R0[sel]), 1)
+    return float(n), float(np.exp(logc))
+
+
+def fit_sqrt_offset(t_tau: np.ndarray, r_R0: np.ndarray, lo: float = 0.05, hi: float = 0.5):
+    """Square-root law with a free time origin, r / R0 = c sqrt(t / tau - t_c):
+    a least-squares line through r^2 over lo <= t/tau <= hi.  Returns c,
+    t_c and the rms residual of r^2 relative to its mean (small when the
+    spreading follows the square-root law; t_c < 0 when the diffuse
+    interfaces of drop and film merge before the geometric contact)."""
+    sel = (t_tau >= lo) & (t_tau <= hi) & (r_R0 > 0)
+    if sel.sum() < 3:
+        raise ValueError("fewer than 3 samples with a crown in the fit window")
+    t, r2 = t_tau[sel], r_R0[sel] ** 2
+    A, B = np.polyfit(t, r2, 1)
+    res = r2 - (A * t + B)
+    return float(np.sqrt(max(A, 0.0))), float(-B / A), float(np.sqrt(np.mean(res ** 2)) / np.mean(r2))
+
+
+PAPER_2D_IMPACTS = ((57.0, 4000.0), (93.0, 4000.0), (238.0, 4000.0), (93.0, 100.0))   # (We, Re), Sec. 3.2
+
+
+def crown_sweep(cases=PAPER_2D_IMPACTS, R0: float = 100.0, sigma: float | None = None, D: int = 2,
+                t_end: float = 1.0, samples: int = 25, window=(0.04, 0.25), **kw) -> list:
+    """Crown-radius histories of impacts at the (We, Re) pairs, each fitted
+    to r / R0 = c (t / tau)^n over the window of t / tau; sigma defaults to
+    the Laplace-law surface tension of the EOS at the impact temperature.
+    A case that goes unstable is reported with stable = False."""
+    if sigma is None:
+        sigma = surface_tension(W.TR_OF_RATIO[kw.get("ratio", 1000)])
+    out = []
+    for We, Re in cases:
+        w = impact_we_re(We, Re, R0, sigma, D=D, **kw)
+        rec = dict(We=We, Re=Re, R0=R0, D=D, u0=w.u_impact, nu_l=w.nu_liquid, sigma=sigma, stable=True)
+        try:
+            h = crown_history(w, t_end=t_end, samples=samples)
+            rec.update(t_tau=h["t_tau"], r_R0=h["r_R0"], steps=h["steps"])
+            rec["n"], rec["c"] = fit_sqrt(h["t_tau"], h["r_R0"], *window)
+            rec["c_off"], rec["t_c"], rec["resid"] = fit_sqrt_offset(h["t_tau"], h["r_R0"], *window)
+        except E.ElmrtUnstable:
+            rec["stable"] = False
+        out.append(rec)
     return out

@@ -1,0 +1,100 @@
+"""Crown-radius post-processing of drop impacts (Sec. 3.2, 3.3), on
+synthetic density fields whose liquid extent is known in closed form."""
+import numpy as np
+import pytest
+
+from paper_2201_12404_amd import studies as S
+from paper_2201_12404_amd import workloads as W
+
+
+def _field(w, zc, R, sharp=1.0):
+    """Film of thickness w.film plus a drop of radius R centred over the axis
+    at height zc, with tanh interfaces of width 'sharp'."""
+    X = W._coords(w.n)
+    D = w.D
+    r = np.sqrt(sum((X[a] - w.centre[a]) ** 2 for a in range(D - 1)) + (X[D - 1] - zc) ** 2)
+    phi = np.maximum(0.5 * (1 - np.tanh(2 * (X[D - 1] - w.film) / sharp)), 0.5 * (1 - np.tanh(2 * (r - R) / sharp)))
+    return w.rho_v + (w.rho_l - w.rho_v) * phi
+
+
+@pytest.mark.parametrize("D", [2, 3])
+@pytest.mark.parametrize("pen", [3.0, 8.0, 15.0])
+def test_crown_radius_is_the_chord_of_the_drop(D, pen):
+    """A drop that has sunk 'pen' cells below the probe plane: the liquid
+    extent there is the chord 2 sqrt(R^2 - (R - pen)^2) of the sphere."""
+    R = 20.0
+    w = S.impact_we_re(93, 400, R, 0.01, D=D, extent=(6, 3) if D == 2 else (4, 4, 3))
+    zp = round(w.film + w.width)
+    zc = zp + R - pen
+    rho = _field(w, zc, R)
+    expect = np.sqrt(R * R - (R - pen) ** 2)
+    got = S.crown_radius(rho, w)
+    assert abs(got - expect) < 0.35, (got, expect)
+
+
+def test_crown_radius_before_contact_and_full_row():
+    w = S.impact_we_re(93, 400, 20.0, 0.01, extent=(6, 3))
+    rho = _field(w, w.centre[-1], w.radius)        # drop still above the probe row
+    assert S.crown_radius(rho, w) == 0.0
+    rho = np.full(w.N, w.rho_l)                    # liquid across the whole row
+    assert S.crown_radius(rho, w) == w.n[0] / 2.0
+
+
+def test_ray_extent_interpolates_and_finds_the_crown_wall():
+    line = np.zeros(40)
+    line[10:21] = 1.0
+    line[9], line[21] = 0.75, 0.25
+    # rightward from 15: cell 20 (1) to 21 (0.25) crosses 0.5 at 20 + 2/3
+    assert S._ray_extent(line, 15, 1, 0.5) == pytest.approx(20 + 2 / 3 - 15)
+    # leftward: cell 9 (0.75) to 8 (0) crosses at 9 - 1/3
+    assert S._ray_extent(line, 15, -1, 0.5) == pytest.approx(15 - (9 - 1 / 3))
+    # periodic wrap: the same run rolled across the end of the line
+    wrapped = np.roll(line, 25)
+    assert S._ray_extent(wrapped, (15 + 25) % 40, 1, 0.5) == pytest.approx(20 + 2 / 3 - 15)
+    # vapour on the axis (a crater): the ray skips it to the wall's outer edge
+    assert S._ray_extent(line, 4, 1, 0.5) == pytest.approx(20 + 2 / 3 - 4)
+    # no liquid within half the line
+    assert S._ray_extent(np.zeros(40), 3, 1, 0.5) == 0.0
+    assert S._ray_extent(np.ones(40), 3, -1, 0.5) == 20.0
+
+
+def test_crown_radius_of_a_ring():
+    """3-D crown wall: a liquid ring of inner radius 10 and outer radius 14
+    around a vapour crater, in the probe plane: radius 14."""
+    w = S.impact_we_re(93, 400, 20.0, 0.01, D=3, extent=(4, 4, 3))
+    X = W._coords(w.n)
+    r = np.sqrt((X[0] - w.centre[0]) ** 2 + (X[1] - w.centre[1]) ** 2)
+    ring = 0.5 * (np.tanh(2 * (r - 10)) - np.tanh(2 * (r - 14)))
+    rho = w.rho_v + (w.rho_l - w.rho_v) * ring
+    assert S.crown_radius(rho, w) == pytest.approx(14.0, abs=0.3)
+
+
+def test_fit_sqrt_recovers_power_law():
+    t = np.linspace(0.02, 1.0, 40)
+    n, c = S.fit_sqrt(t, 2.0 * np.sqrt(t))
+    assert n == pytest.approx(0.5, abs=1e-12) and c == pytest.approx(2.0, rel=1e-12)
+    n, c = S.fit_sqrt(t, 1.3 * t ** 0.7, lo=0.1, hi=0.9)
+    assert n == pytest.approx(0.7, abs=1e-12) and c == pytest.approx(1.3, rel=1e-12)
+    with pytest.raises(ValueError):
+        S.fit_sqrt(t, np.zeros_like(t))
+
+
+def test_fit_sqrt_offset_recovers_origin_and_flags_other_laws():
+    t = np.linspace(0.05, 0.5, 20)
+    c, tc, res = S.fit_sqrt_offset(t, 3.0 * np.sqrt(t + 0.12))
+    assert c == pytest.approx(3.0, rel=1e-10) and tc == pytest.approx(-0.12, abs=1e-10) and res < 1e-12
+    _, _, res = S.fit_sqrt_offset(t, t ** 0.25)    # a different power law leaves a residual
+    assert res > 1e-2
+
+
+def test_impact_we_re_dimensionless_groups():
+    sigma, R0 = 0.0123, 50.0
+    for D in (2, 3):
+        w = S.impact_we_re(238, 4000, R0, sigma, D=D)
+        We = 2 * w.rho_l * R0 * w.u_impact ** 2 / sigma
+        Re = 2 * w.u_impact * R0 / w.nu_liquid
+        assert We == pytest.approx(238, rel=1e-12) and Re == pytest.approx(4000, rel=1e-12)
+        assert w.nu_vapour == pytest.approx(15 * w.nu_liquid, rel=1e-12)
+        assert w.centre[-1] - w.radius - w.film == pytest.approx(2 * w.width)
+    assert S.impact_we_re(93, 100, R0, sigma).n == (1200, 600)
+    assert S.impact_we_re(93, 100, R0, sigma, D=3).n == (700, 700, 300)

@@ -118,3 +118,39 @@ def test_laplace_law_and_surface_tension_scaling():
     m, c = S.fit_power(temps, s)
     say(f"sigma(T/Tc) {dict(zip(temps, s))}; exponent {m:.3f}")
     assert 1.2 < m < 1.8
+
+
+def test_crown_radius_square_root_law_2d():
+    """2-D drop impact on a film (R0 = 50, box 24 R0 x 12 R0, h = R0,
+    density ratio 1000, U0 = 0.05, nu_l = 0.005, nu_v = 15 nu_l): the crown
+    radius grows as the square root of time in the early stage (Sec. 3.2).
+    Bar: the fitted exponent over 0.04 <= t/tau <= 0.25 within 0.4 .. 0.65
+    (the early-time growth is not yet a pure power law at this resolution:
+    the diffuse interfaces touch before the geometric contact)."""
+    w = S.impact_case(50.0, 0.05, 0.005)
+    h = S.crown_history(w, t_end=0.3, samples=15)
+    n, c = S.fit_sqrt(h["t_tau"], h["r_R0"], 0.04, 0.25)
+    c2, tc, res = S.fit_sqrt_offset(h["t_tau"], h["r_R0"], 0.04, 0.25)
+    say(f"2-D crown: n={n:.3f} c={c:.3f}; sqrt law with origin: c={c2:.3f} t_c={tc:.3f} resid={res:.4f}; "
+        f"r/R0={np.round(h['r_R0'], 3).tolist()}")
+    assert np.all(np.diff(h["r_R0"]) > 0)
+    assert 0.4 < n < 0.65
+
+
+def test_crown_diameter_grows_3d():
+    """3-D drop impact (R0 = 20, box 14 R0 x 14 R0 x 6 R0, h = 0.44 R0,
+    U0 = 0.04, nu_l = 0.005): the crown diameter grows monotonically over
+    0.05 <= t/tau <= 0.4.  Measured from the geometric contact its exponent
+    is low (bar 0.25 .. 0.7): on this thin, barely resolved film the diffuse
+    interfaces merge well before the contact.  With a free time origin the
+    square-root law holds: r^2 linear in t within 3% rms, origin before
+    the geometric contact (t_c < 0.05)."""
+    w = S.impact_case(20.0, 0.04, 0.005, D=3)
+    h = S.crown_history(w, t_end=0.4, samples=8)
+    n, c = S.fit_sqrt(h["t_tau"], h["r_R0"], 0.05, 0.4)
+    c2, tc, res = S.fit_sqrt_offset(h["t_tau"], h["r_R0"], 0.05, 0.4)
+    say(f"3-D crown: n={n:.3f} c={c:.3f}; sqrt law with origin: c={c2:.3f} t_c={tc:.3f} resid={res:.4f}; "
+        f"d/(2 R0)={np.round(h['r_R0'], 3).tolist()}")
+    assert np.all(np.diff(h["r_R0"]) > 0)
+    assert 0.25 < n < 0.7
+    assert res < 0.03 and tc < 0.05
