@@ -138,14 +138,23 @@ elmrt_status elmrt_coexistence(const elmrt_params* p, double* rho_vapour, double
  * n host FP64 densities (post-processing: Laplace pressure jumps). */
 elmrt_status elmrt_pressure(const elmrt_params* p, const double* rho, double* P, int64_t n);
 
+/* Move s to another HIP stream (NULL: the null stream): its later calls
+ * enqueue there.  Work already enqueued for s on the old stream is not moved:
+ * the caller orders it before the new stream's work (synchronise the old
+ * stream, or record an event there and wait for it).  A batch member must
+ * share the batch's stream when it is stepped (rebuild the batch after
+ * moving a member). */
+elmrt_status elmrt_set_stream(elmrt_sim* s, void* stream);
+
 /* Tile shape of the collision kernel: tx x ty cells per workgroup, marched
  * over tm planes along the last axis.  Compiled shapes:
  * D2Q9 ty = 1 with tx = 64, 128 or 256; D3Q27 (tx, ty) = (64, 4), (64, 2),
  * (32, 8) or (128, 2).  Other shapes, or tm < 0, return ELMRT_E_INVALID and
  * leave the tiling unchanged.  tm = 0 (the default, with 64 x 1 or 64 x 4)
- * picks the depth automatically: 16 inside a batch, and for a sim stepped
- * alone the deepest of 16, 8, 4, 2, 1 whose launch still has >= 2048 (D3Q27)
- * or 4096 (D2Q9) wavefronts.  Every tiling gives bitwise the same result. */
+ * picks the depth automatically: the deepest of 16, 8, 4, 2, 1 (at most the
+ * last grid extent) for which the launch -- the sim stepped alone, or all
+ * members of a batch together -- still has >= 2048 (D3Q27) or 4096 (D2Q9)
+ * wavefronts.  Every tiling gives bitwise the same result. */
 elmrt_status elmrt_set_tiling(elmrt_sim* s, int32_t tx, int32_t ty, int32_t tm);
 
 /* Pick the collision tiling of s by measurement: every compiled tile shape
@@ -181,7 +190,8 @@ elmrt_status elmrt_batch_create(elmrt_sim* const* sims, int32_t count, void* dev
                                 size_t workspace_bytes, elmrt_batch** out);
 
 /* Advance every member by nsteps (asynchronous on the members' stream; the
- * graph is captured on a private stream at first use). */
+ * graph is captured on a private stream at first use).  ELMRT_E_STATE if a
+ * member has been moved to another stream since the batch was created. */
 elmrt_status elmrt_batch_step(elmrt_batch* b, int64_t nsteps);
 
 /* use_graph = 0: enqueue the launches directly instead of replaying the
@@ -215,16 +225,22 @@ void elmrt_destroy(elmrt_sim* s);
  * advances by chunk_steps, or by the fewest steps any of them still needs,
  * so every job stops exactly at its step count; small jobs share rounds,
  * large ones take turns.
- * Finished jobs are read out (fields and sums kept on the host until
- * elmrt_server_result) and their memory goes back to the pool before the
- * next admission.  A job's result is bitwise the same
- * as the same simulation run alone.  The server owns its job records; the
- * pool and the stream are the caller's and must outlive it.  Not thread-safe:
- * one thread drives a server. */
+ * A round first enqueues its steps on the compute stream (the caller's);
+ * while the device works it reads out the jobs whose last steps were
+ * enqueued in earlier rounds (fields and sums kept on the host until
+ * elmrt_server_result), returns their memory to the pool, and uploads and
+ * initialises newly admitted jobs, both on a second stream the server
+ * creates (non-blocking, default priority); admitted jobs join the next
+ * round.  A job's result is bitwise the same as the same simulation run
+ * alone.  The server owns its job records; the pool and the stream are the
+ * caller's and must outlive it.  Not thread-safe: one thread drives a
+ * server. */
 typedef struct elmrt_server elmrt_server;
 
 /* dev_pool: device memory (256-byte aligned, >= 4096 bytes) the server carves
- * job workspaces and batch tables from; stream: hipStream_t or NULL. */
+ * job workspaces and batch tables from; stream: hipStream_t or NULL, the
+ * compute stream.  ELMRT_E_DEVICE if the server's own stream or events cannot
+ * be created. */
 elmrt_status elmrt_server_create(void* dev_pool, size_t pool_bytes, void* stream, int64_t chunk_steps,
                                  elmrt_server** out);
 
@@ -240,9 +256,10 @@ elmrt_status elmrt_server_set_policy(elmrt_server* s, int32_t policy);
 elmrt_status elmrt_server_submit(elmrt_server* s, const elmrt_params* p, const double* rho0, const double* u0,
                                  int64_t steps, int64_t* job_id);
 
-/* Run up to 'rounds' rounds (admission, one batched advance per lattice and
- * precision, retirement); returns early when no job is queued or resident.
- * *queued, *resident (may be NULL) count the jobs waiting and on the device. */
+/* Run up to 'rounds' rounds (one batched advance per lattice and precision,
+ * retirement of jobs finished earlier, admission); returns early when no job
+ * is queued or resident.  *queued, *resident (may be NULL) count the jobs
+ * waiting and on the device (including finished ones not yet read out). */
 elmrt_status elmrt_server_run(elmrt_server* s, int32_t rounds, int32_t* queued, int32_t* resident);
 
 /* State of a job (0 queued, 1 resident, 2 done, 3 failed), its submit /

@@ -264,7 +264,7 @@ elmrt_status elmrt_create(const elmrt_params* p, void* ws, size_t ws_bytes, void
     s->initialised = false;
     s->tx = 64;
     s->ty = s->D == 3 ? 4 : 1;
-    s->tm = 0;   // automatic marching depth (collide_depth)
+    s->tm = 0;   // automatic marching depth (auto_depth)
     // physics constants (host FP64; cast to the working precision at launch)
     PengRobinson pr(p->eos_a, p->eos_b, p->eos_R, p->acentric, p->T_over_Tc);
     s->ph.RT = pr.RT;
@@ -326,24 +326,33 @@ elmrt_status elmrt_init_fields(elmrt_sim* s, const double* rho0, const double* u
     return ELMRT_OK;
 }
 
-// Marching depth of the collision tiles.  An explicit depth is used as set.
-// The automatic depth is 16 planes inside a batch (whose launch has work to
-// spare) and, for a grid launched alone, the deepest of 16, 8, 4, 2, 1 that
-// still gives min_waves wavefronts: on small grids a deep march leaves compute
-// units idle, a shallow one recomputes psi on the 4 halo planes of every tile.
-// The thresholds are measured (64^3..256^3 and 128^2..1024^2 impacts): about
-// two thirds of the wavefronts the chip holds at each kernel's occupancy (3
-// per SIMD for D3Q27 FP32, 5 for D2Q9).
-static int collide_depth(const elmrt_sim* s, bool batched)
+// Marching depth of the collision tiles.  A deep march amortises the psi
+// recomputation on the 4 halo planes of every tile; a shallow one gives small
+// launches enough workgroups.  An explicit depth is used as set.  The
+// automatic depth of a launch (one grid, or all members of a batch) is the
+// deepest of 16, 8, 4, 2, 1 whose launch still holds min_waves wavefronts,
+// about two thirds of what the chip holds at each kernel's occupancy (3 per
+// SIMD for D3Q27 FP32, 5 for D2Q9); the thresholds are measured on 64^3..256^3
+// and 128^2..1024^2 impacts.  Members never march deeper than their grid.
+static int member_depth(const elmrt_sim* s, int cap)
 {
-    if (s->tm > 0) return s->tm;
-    int tm = std::min(16, s->L.g.n[s->D - 1]);
-    if (batched) return tm;
-    const long long min_waves = s->D == 3 ? 2048 : 4096;
-    const long long waves_per_block = (s->tx * s->ty + 63) / 64;
-    while (tm > 1 && elmrt::collide_tiling(s->D, s->L.g, s->tx, s->ty, tm).blocks * waves_per_block < min_waves)
-        tm /= 2;
-    return tm;
+    return s->tm > 0 ? s->tm : std::min(cap, s->L.g.n[s->D - 1]);
+}
+static int auto_depth(elmrt_sim* const* sims, size_t count)
+{
+    if (count == 0) return 16;
+    const long long min_waves = sims[0]->D == 3 ? 2048 : 4096;
+    int cap = 16;
+    for (; cap > 1; cap /= 2) {
+        long long waves = 0;
+        for (size_t k = 0; k < count; ++k) {
+            const elmrt_sim* s = sims[k];
+            const long long per_block = (s->tx * s->ty + 63) / 64;
+            waves += elmrt::collide_tiling(s->D, s->L.g, s->tx, s->ty, member_depth(s, cap)).blocks * per_block;
+        }
+        if (waves >= min_waves) break;
+    }
+    return cap;
 }
 
 // Enqueue nsteps steps.  With ev != NULL (2*nsteps + 1 events) an event is
@@ -356,13 +365,14 @@ static elmrt_status step_impl(elmrt_sim* s, int64_t nsteps, hipEvent_t* ev)
     if (!s->initialised) return fail(ELMRT_E_STATE, "elmrt_init_fields has not been called");
     hipError_t e;
     if (ev && (e = hipEventRecord(ev[0], s->stream)) != hipSuccess) return hip_fail(e, "hipEventRecord");
+    const int cap = auto_depth(&s, 1);
     for (int64_t k = 0; k < nsteps; ++k) {
         void* cur = s->buf[s->cur];
         void* nxt = s->buf[1 - s->cur];
         e = elmrt::launch_macro(s->L, cur, s->rho, s->q, s->flag);
         if (e != hipSuccess) return hip_fail(e, "moment kernel");
         if (ev && (e = hipEventRecord(ev[2 * k + 1], s->stream)) != hipSuccess) return hip_fail(e, "hipEventRecord");
-        e = elmrt::launch_collide(s->L, s->tx, s->ty, collide_depth(s, false), cur, nxt, s->rho, s->q, s->ph);
+        e = elmrt::launch_collide(s->L, s->tx, s->ty, member_depth(s, cap), cur, nxt, s->rho, s->q, s->ph);
         if (e != hipSuccess) return hip_fail(e, "collision kernel");
         if (ev && (e = hipEventRecord(ev[2 * k + 2], s->stream)) != hipSuccess) return hip_fail(e, "hipEventRecord");
         s->cur = 1 - s->cur;
@@ -502,6 +512,14 @@ elmrt_status elmrt_pressure(const elmrt_params* p, const double* rho, double* P,
     if (!(p->T_over_Tc > 0)) return fail(ELMRT_E_INVALID, "T/Tc must be > 0");
     PengRobinson pr(p->eos_a, p->eos_b, p->eos_R, p->acentric, p->T_over_Tc);
     for (int64_t k = 0; k < n; ++k) P[k] = pr.P(rho[k]);
+    return ELMRT_OK;
+}
+
+elmrt_status elmrt_set_stream(elmrt_sim* s, void* stream)
+{
+    if (!s) return fail(ELMRT_E_INVALID, "sim is NULL");
+    s->stream = (hipStream_t)stream;
+    s->L.stream = s->stream;
     return ELMRT_OK;
 }
 
@@ -650,6 +668,7 @@ elmrt_status batch_build(elmrt_batch* b)
     b->hjobs.assign(n, elmrt::BatchJob{});
     b->groups.clear();
     long long mfirst = 0, cfirst = 0;
+    const int cap = auto_depth(b->sims.data(), b->sims.size());
     for (int k = 0; k < n; ++k) {
         const elmrt_sim* s = b->sims[b->order[k]];
         if (b->groups.empty() || b->groups.back().tx != s->tx || b->groups.back().ty != s->ty) {
@@ -665,7 +684,7 @@ elmrt_status batch_build(elmrt_batch* b)
         J.g = s->L.g;
         J.ph = s->ph;
         const elmrt::Tiling mt = elmrt::macro_tiling(s->D, s->L.g, false);
-        const int tm = collide_depth(s, true);
+        const int tm = member_depth(s, cap);
         const elmrt::Tiling ct = elmrt::collide_tiling(s->D, s->L.g, s->tx, s->ty, tm);
         J.mbx = mt.bx;
         J.mby = mt.by;
@@ -826,6 +845,8 @@ elmrt_status elmrt_batch_step(elmrt_batch* b, int64_t nsteps)
 {
     if (!b) return fail(ELMRT_E_INVALID, "batch is NULL");
     if (nsteps < 0) return fail(ELMRT_E_INVALID, "nsteps < 0");
+    for (const elmrt_sim* s : b->sims)
+        if (s->stream != b->stream) return fail(ELMRT_E_STATE, "a member was moved to another stream");
     return batch_step_impl(b, nsteps);
 }
 

@@ -5,9 +5,11 @@
 // policy order (arrival, or least remaining work), up to a budget of cells
 // that occupies the device, form one batch per lattice and
 // precision (elmrt_batch_*) that advances by the chunk or by the fewest steps
-// any member still needs, so that jobs finish exactly; finished jobs are read
-// out and their memory returns to the pool, after which queued jobs are
-// admitted.  Built on the public entry points only.
+// any member still needs, so that jobs finish exactly.  Host transfers overlap
+// the device work: a round first enqueues its steps on the compute stream,
+// then reads out the jobs that finished in earlier rounds and uploads newly
+// admitted ones on a second stream of the server's own; finished jobs' memory
+// returns to the pool once read out.  Built on the public entry points only.
 #include "../../include/elmrt.h"
 #include "elmrt_internal.h"
 
@@ -96,6 +98,7 @@ struct Job {
     size_t N = 0;
     std::vector<double> rho0, u0;      // host inputs until admission
     int64_t steps = 0, done = 0;
+    int64_t last_round = -1;            // round that enqueued the job's last steps
     size_t off = 0, bytes = 0;
     elmrt_sim* sim = nullptr;
     JobState state = QUEUED;
@@ -117,7 +120,11 @@ struct Group {                          // resident jobs of one (lattice, precis
 struct elmrt_server {
     char* pool_base = nullptr;
     std::unique_ptr<Pool> pool;
-    hipStream_t stream = nullptr;
+    hipStream_t stream = nullptr;       // compute: the batches of resident jobs
+    hipStream_t io = nullptr;           // uploads of admitted jobs, read-outs of finished ones
+    hipEvent_t ev[2] = {nullptr, nullptr};   // end of each round's compute, alternating
+    bool ev_recorded[2] = {false, false};
+    int64_t round = 0;
     int64_t chunk = 100;
     int64_t fill = 4 << 20;             // cells advanced per round (at least one job)
     int32_t policy = 1;                 // 0 arrival order, 1 shortest remaining work first
@@ -130,10 +137,15 @@ struct elmrt_server {
 
     ~elmrt_server()
     {
+        (void)hipStreamSynchronize(stream);
+        if (io) (void)hipStreamSynchronize(io);
         for (auto& g : groups)
             if (g.batch) elmrt_batch_destroy(g.batch);
         for (auto& kv : jobs)
             if (kv.second->sim) elmrt_destroy(kv.second->sim);
+        for (hipEvent_t e : ev)
+            if (e) (void)hipEventDestroy(e);
+        if (io) (void)hipStreamDestroy(io);
     }
 };
 
@@ -147,8 +159,11 @@ elmrt_status admit(elmrt_server* s)
         if (!s->pool->alloc(j->bytes, &off)) break;   // arrival order: wait for memory
         s->queue.pop_front();
         j->off = off;
-        elmrt_status st = elmrt_create(&j->p, s->pool_base + off, j->bytes, s->stream, &j->sim);
+        // upload and initialise on the io stream (init_fields waits for it),
+        // then hand the job to the compute stream
+        elmrt_status st = elmrt_create(&j->p, s->pool_base + off, j->bytes, s->io, &j->sim);
         if (st == ELMRT_OK) st = elmrt_init_fields(j->sim, j->rho0.data(), j->u0.data());
+        if (st == ELMRT_OK) st = elmrt_set_stream(j->sim, s->stream);
         j->rho0.clear();
         j->rho0.shrink_to_fit();
         j->u0.clear();
@@ -169,8 +184,11 @@ elmrt_status admit(elmrt_server* s)
     return ELMRT_OK;
 }
 
+// Read out a finished job on the io stream (its steps on the compute stream
+// are complete) and return its memory to the pool.
 elmrt_status retire(elmrt_server* s, Job* j)
 {
+    elmrt_set_stream(j->sim, s->io);
     j->rho.assign(j->N, 0.0);
     j->u.assign((size_t)j->D * j->N, 0.0);
     const elmrt_status st = elmrt_read_macros(j->sim, j->rho.data(), j->u.data(), j->sums);
@@ -203,15 +221,25 @@ elmrt_status sync_batch(elmrt_server* s, Group& g, const std::vector<Job*>& memb
     return elmrt_batch_create(sims.data(), (int32_t)sims.size(), s->pool_base + g.off, bytes, &g.batch);
 }
 
+// Wait until the compute enqueued by the previous rounds is complete.
+elmrt_status wait_compute(elmrt_server* s, int slot)
+{
+    if (!s->ev_recorded[slot]) return ELMRT_OK;
+    const hipError_t e = hipEventSynchronize(s->ev[slot]);
+    if (e != hipSuccess) return sfail(ELMRT_E_DEVICE, std::string("hipEventSynchronize: ") + hipGetErrorString(e));
+    return ELMRT_OK;
+}
+
 elmrt_status round_once(elmrt_server* s)
 {
-    elmrt_status st = admit(s);
-    if (st != ELMRT_OK) return st;
-    // This round advances resident jobs, in policy order (arrival, or least
-    // remaining work -- cells x steps -- first), until their cells reach the
-    // fill budget: enough work to occupy the device, while the others wait
-    // their turn instead of slowing every running one down.
-    std::vector<Job*> order = s->resident;
+    const int cur = (int)(s->round & 1), prev = cur ^ 1;
+    // This round advances resident jobs with steps left, in policy order
+    // (arrival, or least remaining work -- cells x steps -- first), until their
+    // cells reach the fill budget: enough work to occupy the device, while the
+    // others wait their turn instead of slowing every running one down.
+    std::vector<Job*> order;
+    for (Job* j : s->resident)
+        if (j->done < j->steps) order.push_back(j);
     if (s->policy == 1)
         std::stable_sort(order.begin(), order.end(), [](const Job* a, const Job* b) {
             return (double)a->N * (double)(a->steps - a->done) < (double)b->N * (double)(b->steps - b->done);
@@ -223,40 +251,46 @@ elmrt_status round_once(elmrt_server* s)
         running.push_back(j);
         cells += (int64_t)j->N;
     }
+    elmrt_status st;
     for (int gi = 0; gi < 4; ++gi) {
         std::vector<Job*> members;
         for (Job* j : running)
             if (2 * j->p.lattice + j->p.precision == gi) members.push_back(j);
-        st = sync_batch(s, s->groups[gi], members);
+        Group& g = s->groups[gi];
+        if (g.batch && members != g.members && (st = wait_compute(s, prev)) != ELMRT_OK) return st;
+        st = sync_batch(s, g, members);
         if (st != ELMRT_OK) return st;
         if (members.empty()) continue;
         int64_t n = s->chunk;
         for (Job* j : members) n = std::min(n, j->steps - j->done);
-        if (n > 0) {
-            st = elmrt_batch_step(s->groups[gi].batch, n);
-            if (st != ELMRT_OK) return st;
-            for (Job* j : members) {
-                j->done += n;
-                s->lattice_updates += (int64_t)j->N * n;
-            }
+        st = elmrt_batch_step(g.batch, n);
+        if (st != ELMRT_OK) return st;
+        for (Job* j : members) {
+            j->done += n;
+            j->last_round = s->round;
+            s->lattice_updates += (int64_t)j->N * n;
         }
     }
-    // retire finished jobs (reads synchronise the stream)
-    std::vector<Job*> keep;
-    for (Job* j : s->resident) {
-        if (j->done >= j->steps) {
-            st = retire(s, j);
-            if (st != ELMRT_OK) return st;
-        } else {
-            keep.push_back(j);
-        }
-    }
+    hipError_t e = hipEventRecord(s->ev[cur], s->stream);
+    if (e != hipSuccess) return sfail(ELMRT_E_DEVICE, std::string("hipEventRecord: ") + hipGetErrorString(e));
+    s->ev_recorded[cur] = true;
+    // while the device works on this round: read out the jobs whose last
+    // steps were enqueued by an earlier round ...
+    std::vector<Job*> keep, finished;
+    for (Job* j : s->resident)
+        (j->done >= j->steps && j->last_round < s->round ? finished : keep).push_back(j);
+    if (!finished.empty() && (st = wait_compute(s, prev)) != ELMRT_OK) return st;
+    for (Job* j : finished)
+        if ((st = retire(s, j)) != ELMRT_OK) return st;
     s->resident.swap(keep);
-    if (s->resident.empty())   // release the last batches and their tables
-        for (auto& g : s->groups) {
-            st = sync_batch(s, g, {});
-            if (st != ELMRT_OK) return st;
-        }
+    // ... and upload the jobs that now fit
+    if ((st = admit(s)) != ELMRT_OK) return st;
+    ++s->round;
+    if (s->resident.empty()) {   // release the last batches and their tables
+        if ((st = wait_compute(s, cur)) != ELMRT_OK) return st;
+        for (auto& g : s->groups)
+            if ((st = sync_batch(s, g, {})) != ELMRT_OK) return st;
+    }
     return ELMRT_OK;
 }
 
@@ -277,6 +311,12 @@ elmrt_status elmrt_server_create(void* dev_pool, size_t pool_bytes, void* stream
     s->pool.reset(new Pool(pool_bytes));
     s->stream = (hipStream_t)stream;
     s->chunk = chunk_steps;
+    hipError_t e = hipStreamCreateWithFlags(&s->io, hipStreamNonBlocking);
+    for (int k = 0; k < 2 && e == hipSuccess; ++k) e = hipEventCreateWithFlags(&s->ev[k], hipEventDisableTiming);
+    if (e != hipSuccess) {
+        delete s;
+        return sfail(ELMRT_E_DEVICE, std::string("server streams: ") + hipGetErrorString(e));
+    }
     *out = s;
     return ELMRT_OK;
 }

@@ -66,6 +66,7 @@ _SIGS = {
     "elmrt_coexistence": (ctypes.c_int, [ctypes.POINTER(elmrt_params), _dp, _dp, _dp]),
     "elmrt_pressure": (ctypes.c_int, [ctypes.POINTER(elmrt_params), _dp, _dp, ctypes.c_int64]),
     "elmrt_set_tiling": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_int32, ctypes.c_int32, ctypes.c_int32]),
+    "elmrt_set_stream": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p]),
     "elmrt_autotune": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_int32, ctypes.POINTER(ctypes.c_int64)]),
     "elmrt_batch_workspace_bytes": (ctypes.c_int, [ctypes.c_int32, ctypes.POINTER(ctypes.c_size_t)]),
     "elmrt_batch_create": (ctypes.c_int, [ctypes.POINTER(ctypes.c_void_p), ctypes.c_int32, ctypes.c_void_p,
@@ -277,6 +278,10 @@ def elmrt_pressure(p: Params, rho: np.ndarray) -> np.ndarray:
     P = np.zeros_like(rho)
     _check(lib().elmrt_pressure(ctypes.byref(cp), _dptr(rho), _dptr(P), rho.size))
     return P
+
+
+def elmrt_set_stream(sim: int, stream_ptr: int) -> None:
+    _check(lib().elmrt_set_stream(ctypes.c_void_p(sim), ctypes.c_void_p(stream_ptr)))
 
 
 def elmrt_set_tiling(sim: int, tx: int, ty: int, tm: int) -> None:
