@@ -441,6 +441,12 @@ class Simulation:
     def set_tiling(self, tx, ty, tm):
         elmrt_set_tiling(self.handle, tx, ty, tm)
 
+    def set_stream(self, stream):
+        """Enqueue later calls on ``stream`` (a torch.cuda.Stream); work
+        already enqueued on the old stream must be ordered by the caller."""
+        elmrt_set_stream(self.handle, stream.cuda_stream)
+        self.stream = stream
+
     def autotune(self, trial_steps: int = 4) -> int:
         return elmrt_autotune(self.handle, trial_steps)
 

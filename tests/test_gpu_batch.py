@@ -164,3 +164,33 @@ def test_batch_rejects_mixed_members():
         E.Batch([a, c])
     with pytest.raises(E.ElmrtError, match="twice"):
         E.Batch([a, a])
+
+
+def test_set_stream_keeps_results_and_batch_rejects_a_moved_member():
+    """A simulation moved to another stream mid-run (after synchronising the
+    old one) ends bitwise where the same simulation stepped on one stream
+    ends; a batch refuses to step once a member has moved away from its
+    stream."""
+    import torch
+    w = drops(count=1, hi=96)[0]
+    a, b = make(w), make(w)
+    other = torch.cuda.Stream()
+    a.step(5)
+    torch.cuda.current_stream().synchronize()
+    a.set_stream(other)
+    a.step(7)
+    other.synchronize()
+    b.step(12)
+    ra, ua, sa = a.read_macros()
+    rb, ub, sb = b.read_macros()
+    assert np.array_equal(ra, rb) and np.array_equal(ua, ub) and np.array_equal(sa, sb)
+    c, d = make(w), make(w)
+    batch = E.Batch([c, d])
+    batch.step(2)
+    torch.cuda.current_stream().synchronize()
+    c.set_stream(other)
+    with pytest.raises(E.ElmrtError, match="another stream"):
+        batch.step(2)
+    batch.close()
+    for s in (a, b, c, d):
+        s.close()
