@@ -123,6 +123,14 @@ elmrt_status elmrt_read_macros(elmrt_sim* s, double* rho, double* u, double* sum
  * currents (Sec. 3.1.2).  Same errors as elmrt_read_macros. */
 elmrt_status elmrt_read_fluid_velocity(elmrt_sim* s, double* u);
 
+/* Number of cell updates since elmrt_init_fields in which the entropic
+ * gamma fell back to 2/omega, i.e. h was relaxed to equilibrium because some
+ * f*_i <= 0 or <dh|dh> <= eps^2 rho with eps = 2^-53 (Sec. 2.4; the
+ * stabiliser is undefined there).  0 for BGK.  The test of <dh|dh> is taken in
+ * the build's working precision, so the FP32 and FP64 builds may count
+ * differently near equilibrium.  Synchronises the stream. */
+elmrt_status elmrt_gamma_fallbacks(elmrt_sim* s, int64_t* cells);
+
 /* Read the populations f_i(r, t) (post-streaming) into host FP64 f[i*N + cell]. */
 elmrt_status elmrt_read_populations(elmrt_sim* s, double* f);
 

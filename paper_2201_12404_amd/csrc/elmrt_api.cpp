@@ -372,7 +372,7 @@ static elmrt_status step_impl(elmrt_sim* s, int64_t nsteps, hipEvent_t* ev)
         e = elmrt::launch_macro(s->L, cur, s->rho, s->q, s->flag);
         if (e != hipSuccess) return hip_fail(e, "moment kernel");
         if (ev && (e = hipEventRecord(ev[2 * k + 1], s->stream)) != hipSuccess) return hip_fail(e, "hipEventRecord");
-        e = elmrt::launch_collide(s->L, s->tx, s->ty, member_depth(s, cap), cur, nxt, s->rho, s->q, s->ph);
+        e = elmrt::launch_collide(s->L, s->tx, s->ty, member_depth(s, cap), cur, nxt, s->rho, s->q, s->ph, s->flag);
         if (e != hipSuccess) return hip_fail(e, "collision kernel");
         if (ev && (e = hipEventRecord(ev[2 * k + 2], s->stream)) != hipSuccess) return hip_fail(e, "hipEventRecord");
         s->cur = 1 - s->cur;
@@ -512,6 +512,18 @@ elmrt_status elmrt_pressure(const elmrt_params* p, const double* rho, double* P,
     if (!(p->T_over_Tc > 0)) return fail(ELMRT_E_INVALID, "T/Tc must be > 0");
     PengRobinson pr(p->eos_a, p->eos_b, p->eos_R, p->acentric, p->T_over_Tc);
     for (int64_t k = 0; k < n; ++k) P[k] = pr.P(rho[k]);
+    return ELMRT_OK;
+}
+
+elmrt_status elmrt_gamma_fallbacks(elmrt_sim* s, int64_t* cells)
+{
+    if (!s || !cells) return fail(ELMRT_E_INVALID, "NULL argument");
+    if (!s->initialised) return fail(ELMRT_E_STATE, "elmrt_init_fields has not been called");
+    unsigned long long n = 0;
+    hipError_t e = hipMemcpyAsync(&n, elmrt::gamma_fallbacks(s->flag), sizeof(n), hipMemcpyDeviceToHost, s->stream);
+    if (e == hipSuccess) e = hipStreamSynchronize(s->stream);
+    if (e != hipSuccess) return hip_fail(e, "gamma fall-back count");
+    *cells = (int64_t)n;
     return ELMRT_OK;
 }
 

@@ -9,6 +9,14 @@
 
 namespace elmrt {
 
+// Each simulation's 256-byte flag block holds the sticky instability flag
+// (first 32-bit word) and, at byte 8, a 64-bit count of the cell updates
+// whose entropic gamma fell back to 2/omega.
+__host__ __device__ inline unsigned long long* gamma_fallbacks(unsigned* flag)
+{
+    return reinterpret_cast<unsigned long long*>(reinterpret_cast<char*>(flag) + 8);
+}
+
 // Grid description passed by value to every kernel.
 struct Grid {
     int n[3];      // nx, ny, nz (nz = 1 in 2-D)
@@ -60,7 +68,7 @@ struct Launch {
 hipError_t launch_macro(const Launch& L, const void* cur, void* rho, void* q, unsigned* flag);
 
 hipError_t launch_collide(const Launch& L, int tx, int ty, int tm, const void* cur, void* nxt,
-                          const void* rho, const void* q, const Phys<double>& ph);
+                          const void* rho, const void* q, const Phys<double>& ph, unsigned* flag);
 
 // u0 -= F(rho0) / (2 rho0) in place (fluid velocity -> bare velocity).
 hipError_t launch_shift_velocity(const Launch& L, const double* rho0, double* u0, const Phys<double>& ph);

@@ -284,8 +284,8 @@ __device__ __forceinline__ void conserve_mass(T (&f)[Lat<D>::Q], A rho)
     f[REST] = (T)(rho - M);
 }
 
-// Collision of one cell.  f: pulled populations (overwritten with f').
-// Storage is T.  The per-cell scalars (moments, velocity, force terms, Phi,
+// Collision of one cell.  f: pulled populations (overwritten with f');
+// returns whether the entropic gamma fell back to 2/omega.  Storage is T.  The per-cell scalars (moments, velocity, force terms, Phi,
 // omega, the per-axis factors of the product forms) and the large
 // per-population terms f^eq and f* are formed in A (FP64); the small terms
 // f - f^eq, s, h and the scalar products stay in T; f' is rounded once.  In
@@ -300,7 +300,7 @@ __device__ __forceinline__ void conserve_mass(T (&f)[Lat<D>::Q], A rho)
 // e_z A(x,y) + phi2_z B(x,y) + phi1_z C(x,y), where A, B, C collect the 1-D
 // dual functions of the x and y axes.
 template <int D, typename T, typename A>
-__device__ __forceinline__ void collide(T (&f)[Lat<D>::Q], A rho, const A (&j)[3], const A (&F)[3],
+__device__ __forceinline__ bool collide(T (&f)[Lat<D>::Q], A rho, const A (&j)[3], const A (&F)[3],
                                         const A (&Phi)[3], A omega, int entropic)
 {
     constexpr int Q = Lat<D>::Q;
@@ -387,7 +387,7 @@ __device__ __forceinline__ void collide(T (&f)[Lat<D>::Q], A rho, const A (&j)[3
                 }
             }
         if constexpr (sizeof(T) < sizeof(A)) conserve_mass<D, T, A>(f, rho);
-        return;
+        return false;
     }
     // trace in h: s carries the deviatoric part only
     {
@@ -446,7 +446,8 @@ __device__ __forceinline__ void collide(T (&f)[Lat<D>::Q], A rho, const A (&j)[3
         H += h * hw;
         f[i] = h;
     }
-    const T ch = (pos && (A)H > Eps2<A>::v * rho) ? (T)(omega - A(1)) * S * rcp<T>(H) : T(0);
+    const bool entropic_gamma = pos && (A)H > Eps2<A>::v * rho;
+    const T ch = entropic_gamma ? (T)(omega - A(1)) * S * rcp<T>(H) : T(0);
     // f' = f* + (1 - omega) s + (1 - omega gamma/2) h, f* from rho times its
     // x-y factor product and the z factor
 #pragma unroll
@@ -461,6 +462,7 @@ __device__ __forceinline__ void collide(T (&f)[Lat<D>::Q], A rho, const A (&j)[3
             }
         }
     if constexpr (sizeof(T) < sizeof(A)) conserve_mass<D, T, A>(f, rho);
+    return !entropic_gamma;
 }
 
 // ------------------------------------------------------------------ kernels
@@ -748,7 +750,8 @@ struct CollideWaves {
 template <int D, typename T, int TX, int TY>
 __device__ __forceinline__ void collide_tile(int b, const T* __restrict__ cur, T* __restrict__ nxt,
                                              const T* __restrict__ rho, const T* __restrict__ q, const Grid& g,
-                                             const Phys<double>& ph, int bx, int by, int tm)
+                                             const Phys<double>& ph, int bx, int by, int tm,
+                                             unsigned long long* __restrict__ fallbacks)
 {
     constexpr int Q = Lat<D>::Q;
     constexpr int HX = TX + 4;
@@ -923,7 +926,12 @@ __device__ __forceinline__ void collide_tile(int b, const T* __restrict__ cur, T
                 F[a] = 2.0 * (double)c0.psi * G[a] + ph.kappa * rhoc * K[a];
                 Phi[a] = half_rate * dq[a];
             }
-            collide<D, T, double>(f, rhoc, j, F, Phi, omega, ph.entropic);
+            const bool fell_back = collide<D, T, double>(f, rhoc, j, F, Phi, omega, ph.entropic);
+            // count the cells whose gamma fell back: one atomic per wavefront
+            // and plane, only when some lane did
+            const unsigned long long fb = __ballot(fell_back);
+            if (fb != 0ull && __lane_id() == (unsigned)(__ffsll((long long)fb) - 1))
+                atomicAdd(fallbacks, (unsigned long long)__popcll(fb));
             {
                 const uint32_t pb = opaque(P.bytes);
                 const auto R = block_of<D, T>(nxt, P, P.m);
@@ -947,9 +955,9 @@ __global__ __launch_bounds__(TX* TY) void k_macro(const T* __restrict__ cur, T* 
 template <int D, typename T, int TX, int TY>
 __global__ __launch_bounds__(TX* TY) __attribute__((amdgpu_waves_per_eu(CollideWaves<D, T>::v))) void k_collide(
     const T* __restrict__ cur, T* __restrict__ nxt, const T* __restrict__ rho, const T* __restrict__ q, Grid g,
-    Phys<double> ph, int bx, int by, int tm)
+    Phys<double> ph, int bx, int by, int tm, unsigned long long* __restrict__ fallbacks)
 {
-    collide_tile<D, T, TX, TY>((int)blockIdx.x, cur, nxt, rho, q, g, ph, bx, by, tm);
+    collide_tile<D, T, TX, TY>((int)blockIdx.x, cur, nxt, rho, q, g, ph, bx, by, tm, fallbacks);
 }
 
 // Batched entry points: the workgroups of one launch cover the tiles of every
@@ -985,7 +993,8 @@ __global__ __launch_bounds__(TX* TY) __attribute__((amdgpu_waves_per_eu(CollideW
     const int j = job_of(jobs, njobs, b, &BatchJob::cfirst);
     const BatchJob& J = jobs[j];
     collide_tile<D, T, TX, TY>(b - J.cfirst, (const T*)J.buf[J.cur0 ^ parity], (T*)J.buf[J.cur0 ^ parity ^ 1],
-                               (const T*)J.rho, (const T*)J.q, J.g, J.ph, J.cbx, J.cby, J.ctm);
+                               (const T*)J.rho, (const T*)J.q, J.g, J.ph, J.cbx, J.cby, J.ctm,
+                               gamma_fallbacks(J.flag));
 }
 
 // Velocity shift between the bare velocity u = sum c f / rho and the fluid
@@ -1145,12 +1154,13 @@ unsigned flat_blocks(const Grid& g) { return (unsigned)(((long long)g.N + 255) /
 
 template <int D, typename T, int TX, int TY>
 hipError_t collide_t(const Launch& L, int tm, const void* cur, void* nxt, const void* rho, const void* q,
-                     const Phys<double>& ph)
+                     const Phys<double>& ph, unsigned* flag)
 {
     const Tiling t = collide_tiling(D, L.g, TX, TY, tm);
     if (t.blocks <= 0 || t.blocks > 0x7fffffffLL) return hipErrorInvalidConfiguration;
     hipLaunchKernelGGL((k_collide<D, T, TX, TY>), dim3((unsigned)t.blocks), dim3(TX, TY), 0, L.stream,
-                       (const T*)cur, (T*)nxt, (const T*)rho, (const T*)q, L.g, ph, t.bx, t.by, tm);
+                       (const T*)cur, (T*)nxt, (const T*)rho, (const T*)q, L.g, ph, t.bx, t.by, tm,
+                       gamma_fallbacks(flag));
     return hipGetLastError();
 }
 
@@ -1166,21 +1176,21 @@ hipError_t collide_batch_t(const BatchJob* jobs, int njobs, long long blocks, in
 // The compiled collision tile shapes, for the single and the batched launch.
 template <int D, typename T>
 hipError_t collide_dispatch(const Launch& L, int tx, int ty, int tm, const void* cur, void* nxt,
-                            const void* rho, const void* q, const Phys<double>& ph)
+                            const void* rho, const void* q, const Phys<double>& ph, unsigned* flag)
 {
     if constexpr (D == 2) {
         if (ty != 1) return hipErrorInvalidValue;
         switch (tx) {
-        case 64: return collide_t<D, T, 64, 1>(L, tm, cur, nxt, rho, q, ph);
-        case 128: return collide_t<D, T, 128, 1>(L, tm, cur, nxt, rho, q, ph);
-        case 256: return collide_t<D, T, 256, 1>(L, tm, cur, nxt, rho, q, ph);
+        case 64: return collide_t<D, T, 64, 1>(L, tm, cur, nxt, rho, q, ph, flag);
+        case 128: return collide_t<D, T, 128, 1>(L, tm, cur, nxt, rho, q, ph, flag);
+        case 256: return collide_t<D, T, 256, 1>(L, tm, cur, nxt, rho, q, ph, flag);
         default: return hipErrorInvalidValue;
         }
     } else {
-        if (tx == 64 && ty == 4) return collide_t<D, T, 64, 4>(L, tm, cur, nxt, rho, q, ph);
-        if (tx == 64 && ty == 2) return collide_t<D, T, 64, 2>(L, tm, cur, nxt, rho, q, ph);
-        if (tx == 32 && ty == 8) return collide_t<D, T, 32, 8>(L, tm, cur, nxt, rho, q, ph);
-        if (tx == 128 && ty == 2) return collide_t<D, T, 128, 2>(L, tm, cur, nxt, rho, q, ph);
+        if (tx == 64 && ty == 4) return collide_t<D, T, 64, 4>(L, tm, cur, nxt, rho, q, ph, flag);
+        if (tx == 64 && ty == 2) return collide_t<D, T, 64, 2>(L, tm, cur, nxt, rho, q, ph, flag);
+        if (tx == 32 && ty == 8) return collide_t<D, T, 32, 8>(L, tm, cur, nxt, rho, q, ph, flag);
+        if (tx == 128 && ty == 2) return collide_t<D, T, 128, 2>(L, tm, cur, nxt, rho, q, ph, flag);
         return hipErrorInvalidValue;
     }
 }
@@ -1274,13 +1284,13 @@ hipError_t launch_macro(const Launch& L, const void* cur, void* rho, void* q, un
 }
 
 hipError_t launch_collide(const Launch& L, int tx, int ty, int tm, const void* cur, void* nxt,
-                          const void* rho, const void* q, const Phys<double>& ph)
+                          const void* rho, const void* q, const Phys<double>& ph, unsigned* flag)
 {
     if (tm < 1) return hipErrorInvalidValue;
-    if (L.D == 2 && !L.fp64) return collide_dispatch<2, float>(L, tx, ty, tm, cur, nxt, rho, q, ph);
-    if (L.D == 2) return collide_dispatch<2, double>(L, tx, ty, tm, cur, nxt, rho, q, ph);
-    if (!L.fp64) return collide_dispatch<3, float>(L, tx, ty, tm, cur, nxt, rho, q, ph);
-    return collide_dispatch<3, double>(L, tx, ty, tm, cur, nxt, rho, q, ph);
+    if (L.D == 2 && !L.fp64) return collide_dispatch<2, float>(L, tx, ty, tm, cur, nxt, rho, q, ph, flag);
+    if (L.D == 2) return collide_dispatch<2, double>(L, tx, ty, tm, cur, nxt, rho, q, ph, flag);
+    if (!L.fp64) return collide_dispatch<3, float>(L, tx, ty, tm, cur, nxt, rho, q, ph, flag);
+    return collide_dispatch<3, double>(L, tx, ty, tm, cur, nxt, rho, q, ph, flag);
 }
 
 hipError_t launch_macro_batch(int D, int fp64, const BatchJob* jobs, int njobs, long long blocks, int parity,

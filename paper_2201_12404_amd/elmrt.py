@@ -67,6 +67,7 @@ _SIGS = {
     "elmrt_pressure": (ctypes.c_int, [ctypes.POINTER(elmrt_params), _dp, _dp, ctypes.c_int64]),
     "elmrt_set_tiling": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_int32, ctypes.c_int32, ctypes.c_int32]),
     "elmrt_set_stream": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p]),
+    "elmrt_gamma_fallbacks": (ctypes.c_int, [ctypes.c_void_p, ctypes.POINTER(ctypes.c_int64)]),
     "elmrt_autotune": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_int32, ctypes.POINTER(ctypes.c_int64)]),
     "elmrt_batch_workspace_bytes": (ctypes.c_int, [ctypes.c_int32, ctypes.POINTER(ctypes.c_size_t)]),
     "elmrt_batch_create": (ctypes.c_int, [ctypes.POINTER(ctypes.c_void_p), ctypes.c_int32, ctypes.c_void_p,
@@ -280,6 +281,12 @@ def elmrt_pressure(p: Params, rho: np.ndarray) -> np.ndarray:
     return P
 
 
+def elmrt_gamma_fallbacks(sim: int) -> int:
+    out = ctypes.c_int64()
+    _check(lib().elmrt_gamma_fallbacks(ctypes.c_void_p(sim), ctypes.byref(out)))
+    return out.value
+
+
 def elmrt_set_stream(sim: int, stream_ptr: int) -> None:
     _check(lib().elmrt_set_stream(ctypes.c_void_p(sim), ctypes.c_void_p(stream_ptr)))
 
@@ -428,6 +435,9 @@ class Simulation:
 
     def read_macros(self):
         return elmrt_read_macros(self.handle, self.params.N, self.params.D)
+
+    def gamma_fallbacks(self) -> int:
+        return elmrt_gamma_fallbacks(self.handle)
 
     def read_density(self):
         return elmrt_read_density(self.handle, self.params.N)

@@ -348,3 +348,37 @@ def test_large_grid_addressing(D):
     say(f"far drop D={D}: window max |rho(K) - rho(0)| = {moved:.3e}, max |big - small| = {np.abs(rb - rs).max():.3e}")
     assert moved > 1e-4
     assert np.array_equal(rb, rs)
+
+
+@pytest.mark.parametrize("prec", [1, 0])
+def test_gamma_fallback_count(prec):
+    """The count of gamma fall-backs (reading R10) against the oracle's, step
+    by step, where the decision is not a matter of roundoff: a stripe moving
+    at u_x = 0.85 makes a factor of f* (2/3 - xi*^2) negative, so those cells
+    fall back in both.  The first step starts from f = f^eq exactly, where
+    <dh|dh> is roundoff and either decision is correct: not compared.  BGK
+    counts nothing."""
+    from dataclasses import replace
+    w = replace(W.STATIC_DROP_FP64.scaled(n=(70, 44), radius=-100.0, film=0.0, centre=(33.0, 22.0),
+                                          name="fast-stripe"), precision=prec, noise=0.0)
+    rho0 = np.full(w.N, 1.0)
+    u0 = np.random.default_rng(5).uniform(-1e-3, 1e-3, (2, w.N))
+    x = np.arange(w.N) % w.n[0]
+    u0[0, (x >= 10) & (x < 20)] = 0.85
+    for collision in (0, 1):
+        sim = E.Simulation(E.params_for(w, collision))
+        sim.init_fields(rho0, u0)
+        counts = [0]
+        for _ in range(3):
+            sim.step(1)
+            counts.append(sim.gamma_fallbacks())
+        sim.close()
+        gpu = [b - a for a, b in zip(counts, counts[1:])]
+        p = oracle_params(w, collision)
+        f = O.init_fluid(p, rho0, u0)
+        ora = [O.step(p, f, 1).cells_gamma_fallback for _ in range(3)]
+        say(f"gamma fall-backs prec={prec} collision={collision}: gpu {gpu} oracle {ora}")
+        if collision == 1:
+            assert gpu == [0, 0, 0]
+        else:
+            assert gpu[1:] == ora[1:] and gpu[1] > 0
