@@ -123,6 +123,27 @@ elmrt_status elmrt_read_macros(elmrt_sim* s, double* rho, double* u, double* sum
  * currents (Sec. 3.1.2).  Same errors as elmrt_read_macros. */
 elmrt_status elmrt_read_fluid_velocity(elmrt_sim* s, double* u);
 
+/* ---- Checkpoints --------------------------------------------------------
+ *
+ * A snapshot holds everything the next steps depend on: the populations of
+ * the current time (in the library's device layout), the instability flag and
+ * the fall-back count, behind a header naming the lattice, precision and
+ * grid.  It lives in caller-owned device memory of elmrt_state_bytes bytes.
+ * Restoring it into any sim of the same lattice, precision and grid and
+ * stepping gives bitwise the same states as the run it was taken from. */
+elmrt_status elmrt_state_bytes(const elmrt_sim* s, size_t* bytes);
+
+/* Copy the current state into dev_dst (device memory, >= elmrt_state_bytes
+ * bytes), asynchronously on the sim's stream.  ELMRT_E_STATE before
+ * elmrt_init_fields. */
+elmrt_status elmrt_save_state(elmrt_sim* s, void* dev_dst, size_t bytes);
+
+/* Replace the state of s by a snapshot (reads its header: synchronises the
+ * stream; the copies are then asynchronous).  ELMRT_E_INVALID for a buffer
+ * that is not a snapshot, or one of a different lattice, precision or grid.
+ * Marks s initialised. */
+elmrt_status elmrt_load_state(elmrt_sim* s, const void* dev_src, size_t bytes);
+
 /* Number of cell updates since elmrt_init_fields in which the entropic
  * gamma fell back to 2/omega, i.e. h was relaxed to equilibrium because some
  * f*_i <= 0 or <dh|dh> <= eps^2 rho with eps = 2^-53 (Sec. 2.4; the

@@ -221,7 +221,20 @@ struct elmrt_sim {
     int tx, ty, tm;
     elmrt::Phys<double> ph;
     elmrt::Launch L;
+    // header of this sim's state snapshots (constant, so an asynchronous copy
+    // may read it at any time)
+    struct StateHeader {
+        uint64_t magic;
+        int32_t lattice, precision, n[3], pad;
+        uint64_t pop_bytes;
+    } snap{};
 };
+
+namespace {
+constexpr uint64_t kStateMagic = 0x31455441544d4c45ull;   // "ELMTATE1", little-endian
+constexpr size_t kFlagBlock = 256;                         // instability flag + fall-back count
+size_t state_bytes_of(const elmrt_sim* s) { return 2 * kAlign + s->Q * s->N * s->es; }
+}  // namespace
 
 extern "C" {
 
@@ -265,6 +278,11 @@ elmrt_status elmrt_create(const elmrt_params* p, void* ws, size_t ws_bytes, void
     s->tx = 64;
     s->ty = s->D == 3 ? 4 : 1;
     s->tm = 0;   // automatic marching depth (auto_depth)
+    s->snap.magic = kStateMagic;
+    s->snap.lattice = p->lattice;
+    s->snap.precision = p->precision;
+    for (int a = 0; a < 3; ++a) s->snap.n[a] = (int32_t)p->n[a];
+    s->snap.pop_bytes = (uint64_t)s->Q * s->N * s->es;
     // physics constants (host FP64; cast to the working precision at launch)
     PengRobinson pr(p->eos_a, p->eos_b, p->eos_R, p->acentric, p->T_over_Tc);
     s->ph.RT = pr.RT;
@@ -512,6 +530,50 @@ elmrt_status elmrt_pressure(const elmrt_params* p, const double* rho, double* P,
     if (!(p->T_over_Tc > 0)) return fail(ELMRT_E_INVALID, "T/Tc must be > 0");
     PengRobinson pr(p->eos_a, p->eos_b, p->eos_R, p->acentric, p->T_over_Tc);
     for (int64_t k = 0; k < n; ++k) P[k] = pr.P(rho[k]);
+    return ELMRT_OK;
+}
+
+elmrt_status elmrt_state_bytes(const elmrt_sim* s, size_t* bytes)
+{
+    if (!s || !bytes) return fail(ELMRT_E_INVALID, "NULL argument");
+    *bytes = state_bytes_of(s);
+    return ELMRT_OK;
+}
+
+// Snapshot layout: [header, 256 B][flag block, 256 B][populations of the
+// current state in the library's plane-blocked layout].
+elmrt_status elmrt_save_state(elmrt_sim* s, void* dev_dst, size_t bytes)
+{
+    if (!s || !dev_dst) return fail(ELMRT_E_INVALID, "NULL argument");
+    if (!s->initialised) return fail(ELMRT_E_STATE, "elmrt_init_fields has not been called");
+    if (bytes < state_bytes_of(s)) return fail(ELMRT_E_INVALID, "snapshot buffer smaller than elmrt_state_bytes()");
+    char* d = (char*)dev_dst;
+    hipError_t e = hipMemcpyAsync(d, &s->snap, sizeof(s->snap), hipMemcpyHostToDevice, s->stream);
+    if (e == hipSuccess) e = hipMemcpyAsync(d + kAlign, s->flag, kFlagBlock, hipMemcpyDeviceToDevice, s->stream);
+    if (e == hipSuccess)
+        e = hipMemcpyAsync(d + 2 * kAlign, s->buf[s->cur], s->snap.pop_bytes, hipMemcpyDeviceToDevice, s->stream);
+    if (e != hipSuccess) return hip_fail(e, "save_state copy");
+    return ELMRT_OK;
+}
+
+elmrt_status elmrt_load_state(elmrt_sim* s, const void* dev_src, size_t bytes)
+{
+    if (!s || !dev_src) return fail(ELMRT_E_INVALID, "NULL argument");
+    if (bytes < state_bytes_of(s)) return fail(ELMRT_E_INVALID, "snapshot smaller than elmrt_state_bytes()");
+    const char* d = (const char*)dev_src;
+    elmrt_sim::StateHeader h{};
+    hipError_t e = hipMemcpyAsync(&h, d, sizeof(h), hipMemcpyDeviceToHost, s->stream);
+    if (e == hipSuccess) e = hipStreamSynchronize(s->stream);
+    if (e != hipSuccess) return hip_fail(e, "load_state header");
+    if (h.magic != kStateMagic) return fail(ELMRT_E_INVALID, "not a state snapshot");
+    if (h.lattice != s->snap.lattice || h.precision != s->snap.precision || h.n[0] != s->snap.n[0] ||
+        h.n[1] != s->snap.n[1] || h.n[2] != s->snap.n[2] || h.pop_bytes != s->snap.pop_bytes)
+        return fail(ELMRT_E_INVALID, "snapshot of a different lattice, precision or grid");
+    e = hipMemcpyAsync(s->flag, d + kAlign, kFlagBlock, hipMemcpyDeviceToDevice, s->stream);
+    if (e == hipSuccess)
+        e = hipMemcpyAsync(s->buf[s->cur], d + 2 * kAlign, s->snap.pop_bytes, hipMemcpyDeviceToDevice, s->stream);
+    if (e != hipSuccess) return hip_fail(e, "load_state copy");
+    s->initialised = true;
     return ELMRT_OK;
 }
 

@@ -68,6 +68,9 @@ _SIGS = {
     "elmrt_set_tiling": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_int32, ctypes.c_int32, ctypes.c_int32]),
     "elmrt_set_stream": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p]),
     "elmrt_gamma_fallbacks": (ctypes.c_int, [ctypes.c_void_p, ctypes.POINTER(ctypes.c_int64)]),
+    "elmrt_state_bytes": (ctypes.c_int, [ctypes.c_void_p, ctypes.POINTER(ctypes.c_size_t)]),
+    "elmrt_save_state": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_size_t]),
+    "elmrt_load_state": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_size_t]),
     "elmrt_autotune": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_int32, ctypes.POINTER(ctypes.c_int64)]),
     "elmrt_batch_workspace_bytes": (ctypes.c_int, [ctypes.c_int32, ctypes.POINTER(ctypes.c_size_t)]),
     "elmrt_batch_create": (ctypes.c_int, [ctypes.POINTER(ctypes.c_void_p), ctypes.c_int32, ctypes.c_void_p,
@@ -281,6 +284,20 @@ def elmrt_pressure(p: Params, rho: np.ndarray) -> np.ndarray:
     return P
 
 
+def elmrt_state_bytes(sim: int) -> int:
+    out = ctypes.c_size_t()
+    _check(lib().elmrt_state_bytes(ctypes.c_void_p(sim), ctypes.byref(out)))
+    return out.value
+
+
+def elmrt_save_state(sim: int, dev_ptr: int, nbytes: int) -> None:
+    _check(lib().elmrt_save_state(ctypes.c_void_p(sim), ctypes.c_void_p(dev_ptr), nbytes))
+
+
+def elmrt_load_state(sim: int, dev_ptr: int, nbytes: int) -> None:
+    _check(lib().elmrt_load_state(ctypes.c_void_p(sim), ctypes.c_void_p(dev_ptr), nbytes))
+
+
 def elmrt_gamma_fallbacks(sim: int) -> int:
     out = ctypes.c_int64()
     _check(lib().elmrt_gamma_fallbacks(ctypes.c_void_p(sim), ctypes.byref(out)))
@@ -435,6 +452,18 @@ class Simulation:
 
     def read_macros(self):
         return elmrt_read_macros(self.handle, self.params.N, self.params.D)
+
+    def save_state(self):
+        """Snapshot of the current state in a new torch uint8 device tensor."""
+        n = elmrt_state_bytes(self.handle)
+        raw = self._torch.empty(n + 256, dtype=self._torch.uint8, device=self.workspace.device)
+        off = (-raw.data_ptr()) % 256
+        snap = raw[off: off + n]
+        elmrt_save_state(self.handle, snap.data_ptr(), n)
+        return snap
+
+    def load_state(self, snap):
+        elmrt_load_state(self.handle, snap.data_ptr(), snap.numel())
 
     def gamma_fallbacks(self) -> int:
         return elmrt_gamma_fallbacks(self.handle)

@@ -382,3 +382,38 @@ def test_gamma_fallback_count(prec):
             assert gpu == [0, 0, 0]
         else:
             assert gpu[1:] == ora[1:] and gpu[1] > 0
+
+
+@pytest.mark.parametrize("D,prec", [(2, 0), (3, 0), (2, 1)])
+def test_checkpoint_resume_bitwise(D, prec):
+    """Run N steps, snapshot, run M more; restoring the snapshot (into the
+    same sim and into a fresh one of the same problem) and running M steps
+    again gives bitwise the state of the straight N + M run, including the
+    fall-back count.  A snapshot of another grid is refused."""
+    w = _small(D, (0, 1) if D == 2 else (0, 0, 1), prec)
+    N, M = 17, 11
+    straight = E.Simulation(E.params_for(w))
+    straight.init_fields(*W.initial_fields(w))
+    straight.step(N + M)
+    ref = straight.read_populations()
+    ref_fb = straight.gamma_fallbacks()
+    straight.close()
+    a = E.Simulation(E.params_for(w))
+    a.init_fields(*W.initial_fields(w))
+    a.step(N)
+    snap = a.save_state()
+    a.step(M)
+    assert np.array_equal(a.read_populations(), ref)
+    a.load_state(snap)
+    a.step(M)
+    assert np.array_equal(a.read_populations(), ref) and a.gamma_fallbacks() == ref_fb
+    b = E.Simulation(E.params_for(w))
+    b.load_state(snap)
+    b.step(M)
+    assert np.array_equal(b.read_populations(), ref) and b.gamma_fallbacks() == ref_fb
+    from dataclasses import replace
+    other = E.Simulation(E.params_for(replace(w, n=tuple(k - 2 for k in w.n))))
+    with pytest.raises(E.ElmrtError, match="different"):
+        other.load_state(snap)
+    for s in (a, b, other):
+        s.close()
