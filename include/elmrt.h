@@ -123,6 +123,13 @@ elmrt_status elmrt_read_macros(elmrt_sim* s, double* rho, double* u, double* sum
  * currents (Sec. 3.1.2).  Same errors as elmrt_read_macros. */
 elmrt_status elmrt_read_fluid_velocity(elmrt_sim* s, double* u);
 
+/* Enqueue on the sim's stream a copy of its sticky instability flag (nonzero
+ * once a non-finite or non-positive density has been seen) into *host_word,
+ * without waiting: the word holds the flag as of the work enqueued before
+ * this call once the stream has reached it.  host_word should be pinned host
+ * memory (hipHostMalloc); a pageable word makes the copy synchronous. */
+elmrt_status elmrt_poll_unstable(elmrt_sim* s, uint32_t* host_word);
+
 /* ---- Checkpoints --------------------------------------------------------
  *
  * A snapshot holds everything the next steps depend on: the populations of
@@ -260,7 +267,11 @@ void elmrt_destroy(elmrt_sim* s);
  * elmrt_server_result), returns their memory to the pool, and uploads and
  * initialises newly admitted jobs, both on a second stream the server
  * creates (non-blocking, default priority); admitted jobs join the next
- * round.  A job's result is bitwise the same as the same simulation run
+ * round.  After its steps in a round, each job's instability flag is copied
+ * to pinned host memory (elmrt_poll_unstable); a job seen unstable is
+ * evicted: it is not advanced further, and is read out (status
+ * ELMRT_E_UNSTABLE, fields as they stand) and its memory freed while the
+ * others continue.  A job's result is bitwise the same as the same simulation run
  * alone.  The server owns its job records; the pool and the stream are the
  * caller's and must outlive it.  Not thread-safe: one thread drives a
  * server. */

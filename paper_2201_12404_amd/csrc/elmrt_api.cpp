@@ -533,6 +533,14 @@ elmrt_status elmrt_pressure(const elmrt_params* p, const double* rho, double* P,
     return ELMRT_OK;
 }
 
+elmrt_status elmrt_poll_unstable(elmrt_sim* s, uint32_t* host_word)
+{
+    if (!s || !host_word) return fail(ELMRT_E_INVALID, "NULL argument");
+    const hipError_t e = hipMemcpyAsync(host_word, s->flag, sizeof(uint32_t), hipMemcpyDeviceToHost, s->stream);
+    if (e != hipSuccess) return hip_fail(e, "poll copy");
+    return ELMRT_OK;
+}
+
 elmrt_status elmrt_state_bytes(const elmrt_sim* s, size_t* bytes)
 {
     if (!s || !bytes) return fail(ELMRT_E_INVALID, "NULL argument");

@@ -5,7 +5,9 @@
 // policy order (arrival, or least remaining work), up to a budget of cells
 // that occupies the device, form one batch per lattice and
 // precision (elmrt_batch_*) that advances by the chunk or by the fewest steps
-// any member still needs, so that jobs finish exactly.  Host transfers overlap
+// any member still needs, so that jobs finish exactly; a job whose
+// instability flag is seen set (polled after every round without waiting) is
+// evicted and read out early.  Host transfers overlap
 // the device work: a round first enqueues its steps on the compute stream,
 // then reads out the jobs that finished in earlier rounds and uploads newly
 // admitted ones on a second stream of the server's own; finished jobs' memory
@@ -99,6 +101,8 @@ struct Job {
     std::vector<double> rho0, u0;      // host inputs until admission
     int64_t steps = 0, done = 0;
     int64_t last_round = -1;            // round that enqueued the job's last steps
+    int slot = -1;                      // word of the pinned flag array, or -1
+    bool unstable = false;              // evicted: its flag was seen set
     size_t off = 0, bytes = 0;
     elmrt_sim* sim = nullptr;
     JobState state = QUEUED;
@@ -125,6 +129,10 @@ struct elmrt_server {
     hipEvent_t ev[2] = {nullptr, nullptr};   // end of each round's compute, alternating
     bool ev_recorded[2] = {false, false};
     int64_t round = 0;
+    // pinned words the running jobs' instability flags are copied into after
+    // every round (elmrt_poll_unstable), read without waiting
+    uint32_t* flags = nullptr;
+    std::vector<int> free_slots;
     int64_t chunk = 100;
     int64_t fill = 4 << 20;             // cells advanced per round (at least one job)
     int32_t policy = 1;                 // 0 arrival order, 1 shortest remaining work first
@@ -146,6 +154,7 @@ struct elmrt_server {
         for (hipEvent_t e : ev)
             if (e) (void)hipEventDestroy(e);
         if (io) (void)hipStreamDestroy(io);
+        if (flags) (void)hipHostFree(flags);
     }
 };
 
@@ -179,6 +188,11 @@ elmrt_status admit(elmrt_server* s)
             continue;
         }
         j->state = RESIDENT;
+        if (!s->free_slots.empty()) {
+            j->slot = s->free_slots.back();
+            s->free_slots.pop_back();
+            s->flags[j->slot] = 0u;
+        }
         s->resident.push_back(j);
     }
     return ELMRT_OK;
@@ -198,6 +212,8 @@ elmrt_status retire(elmrt_server* s, Job* j)
     elmrt_destroy(j->sim);
     j->sim = nullptr;
     s->pool->release(j->off);
+    if (j->slot >= 0) s->free_slots.push_back(j->slot);
+    j->slot = -1;
     return ELMRT_OK;
 }
 
@@ -237,9 +253,12 @@ elmrt_status round_once(elmrt_server* s)
     // (arrival, or least remaining work -- cells x steps -- first), until their
     // cells reach the fill budget: enough work to occupy the device, while the
     // others wait their turn instead of slowing every running one down.
+    // a job whose flag was seen set is evicted: it is not advanced further
+    for (Job* j : s->resident)
+        if (j->slot >= 0 && *(volatile uint32_t*)&s->flags[j->slot] != 0u) j->unstable = true;
     std::vector<Job*> order;
     for (Job* j : s->resident)
-        if (j->done < j->steps) order.push_back(j);
+        if (j->done < j->steps && !j->unstable) order.push_back(j);
     if (s->policy == 1)
         std::stable_sort(order.begin(), order.end(), [](const Job* a, const Job* b) {
             return (double)a->N * (double)(a->steps - a->done) < (double)b->N * (double)(b->steps - b->done);
@@ -269,6 +288,7 @@ elmrt_status round_once(elmrt_server* s)
             j->done += n;
             j->last_round = s->round;
             s->lattice_updates += (int64_t)j->N * n;
+            if (j->slot >= 0 && (st = elmrt_poll_unstable(j->sim, &s->flags[j->slot])) != ELMRT_OK) return st;
         }
     }
     hipError_t e = hipEventRecord(s->ev[cur], s->stream);
@@ -278,7 +298,7 @@ elmrt_status round_once(elmrt_server* s)
     // steps were enqueued by an earlier round ...
     std::vector<Job*> keep, finished;
     for (Job* j : s->resident)
-        (j->done >= j->steps && j->last_round < s->round ? finished : keep).push_back(j);
+        ((j->done >= j->steps || j->unstable) && j->last_round < s->round ? finished : keep).push_back(j);
     if (!finished.empty() && (st = wait_compute(s, prev)) != ELMRT_OK) return st;
     for (Job* j : finished)
         if ((st = retire(s, j)) != ELMRT_OK) return st;
@@ -311,8 +331,11 @@ elmrt_status elmrt_server_create(void* dev_pool, size_t pool_bytes, void* stream
     s->pool.reset(new Pool(pool_bytes));
     s->stream = (hipStream_t)stream;
     s->chunk = chunk_steps;
+    constexpr int kSlots = 4096;
     hipError_t e = hipStreamCreateWithFlags(&s->io, hipStreamNonBlocking);
     for (int k = 0; k < 2 && e == hipSuccess; ++k) e = hipEventCreateWithFlags(&s->ev[k], hipEventDisableTiming);
+    if (e == hipSuccess) e = hipHostMalloc((void**)&s->flags, kSlots * sizeof(uint32_t), hipHostMallocDefault);
+    for (int k = kSlots - 1; k >= 0 && e == hipSuccess; --k) s->free_slots.push_back(k);
     if (e != hipSuccess) {
         delete s;
         return sfail(ELMRT_E_DEVICE, std::string("server streams: ") + hipGetErrorString(e));

@@ -69,6 +69,7 @@ _SIGS = {
     "elmrt_set_stream": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p]),
     "elmrt_gamma_fallbacks": (ctypes.c_int, [ctypes.c_void_p, ctypes.POINTER(ctypes.c_int64)]),
     "elmrt_state_bytes": (ctypes.c_int, [ctypes.c_void_p, ctypes.POINTER(ctypes.c_size_t)]),
+    "elmrt_poll_unstable": (ctypes.c_int, [ctypes.c_void_p, ctypes.POINTER(ctypes.c_uint32)]),
     "elmrt_save_state": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_size_t]),
     "elmrt_load_state": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_size_t]),
     "elmrt_autotune": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_int32, ctypes.POINTER(ctypes.c_int64)]),
@@ -282,6 +283,12 @@ def elmrt_pressure(p: Params, rho: np.ndarray) -> np.ndarray:
     P = np.zeros_like(rho)
     _check(lib().elmrt_pressure(ctypes.byref(cp), _dptr(rho), _dptr(P), rho.size))
     return P
+
+
+def elmrt_poll_unstable(sim: int, word: "ctypes.c_uint32") -> None:
+    """Enqueue a copy of the sim's instability flag into ``word`` (a
+    ctypes.c_uint32; valid once the sim's stream has reached the copy)."""
+    _check(lib().elmrt_poll_unstable(ctypes.c_void_p(sim), ctypes.byref(word)))
 
 
 def elmrt_state_bytes(sim: int) -> int:

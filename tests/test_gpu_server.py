@@ -126,3 +126,36 @@ def test_fill_budget_takes_turns(policy):
         rho_a, u_a, _ = alone(w, steps)
         assert np.array_equal(rho_s, rho_a) and np.array_equal(u_s, u_a)
     srv.close()
+
+
+def test_unstable_job_is_evicted():
+    """A job that goes unstable (BGK at nu = 0.0005 on a density-ratio-1000
+    drop) is evicted once its polled flag is seen: it stops short of its step
+    count, reports ELMRT_E_UNSTABLE with its fields, and frees its memory,
+    while the job beside it finishes bitwise as if run alone."""
+    from paper_2201_12404_amd import studies as S
+    bad_w = S.drop(W.TR_OF_RATIO[1000], 0.0005, N=96, R=20.0)
+    bad_steps = 4000
+    sim = E.Simulation(E.params_for(bad_w, E.ELMRT_BGK))
+    sim.init_fields(*W.initial_fields(bad_w))
+    sim.step(bad_steps)
+    with pytest.raises(E.ElmrtUnstable):
+        sim.read_macros()
+    sim.close()
+    good_w, good_steps = W.impact_job(2, 128, 100, 0.03, 60, 1), 600
+    srv = E.Server(pool_bytes=1 << 28, chunk_steps=20)
+    bad = srv.submit(E.params_for(bad_w, E.ELMRT_BGK), *W.initial_fields(bad_w), bad_steps)
+    good = srv.submit(E.params_for(good_w), *W.initial_fields(good_w), good_steps)
+    while srv.run(1) != (0, 0):
+        pass
+    st, _, done = srv.job(bad)
+    say(f"unstable job evicted after {done} of {bad_steps} steps")
+    assert st == E.Server.DONE and done < bad_steps
+    with pytest.raises(E.ElmrtUnstable) as ei:
+        srv.result(bad)
+    assert ei.value.rho.shape == (bad_w.N,)
+    rho_s, u_s, _ = srv.result(good)
+    rho_a, u_a, _ = alone(good_w, good_steps)
+    assert np.array_equal(rho_s, rho_a) and np.array_equal(u_s, u_a)
+    assert srv.stats()[1] == 1 << 28
+    srv.close()
