@@ -40,15 +40,15 @@ def algorithmic_bytes(D: int, es: int):
     return (Q * es + (1 + D) * es, 2 * Q * es + (1 + D) * es)
 
 
-def measured_traffic(tag: str):
+def measured_traffic(tag: str, tiling):
     """HBM bytes per collision launch from the committed rocprofv3 counter
-    summary, if it was taken on the current kernel source."""
+    summary, if it was taken on the current kernel source with this tiling."""
     path = os.path.join(ROOT, "profiles", f"traffic_{tag}.json")
     if not os.path.exists(path):
         return None
     with open(path) as f:
         d = json.load(f)
-    if d.get("kernel_source_sha") != kernel_source_hash():
+    if d.get("kernel_source_sha") != kernel_source_hash() or d.get("tiling") != list(tiling):
         return None
     return d.get("bytes_per_launch")
 
@@ -228,7 +228,8 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-budget", type=float, default=20.0)
     ap.add_argument("--copy-probe", action="store_true", help="also run a 1 GiB copy kernel (counter calibration)")
-    ap.add_argument("--tile", type=str, default="", help="tx,ty,tm of the collision kernel")
+    ap.add_argument("--tile", type=str, default="", help="tx,ty,tm of the collision kernel (skips the autotuner)")
+    ap.add_argument("--no-autotune", action="store_true", help="keep the library's default tiling")
     ap.add_argument("--no-batched", action="store_true", help="skip the batched and served comparisons")
     ap.add_argument("--serve-jobs", type=int, default=24, help="jobs of the served stream to replay")
     ap.add_argument("--serve-step-scale", type=float, default=0.1, help="scale of the served jobs' step counts")
@@ -250,13 +251,18 @@ def main():
     params = E.params_for(w)
     rho0, u0 = W.initial_fields(w)
     sim = E.Simulation(params)
-    tx, ty, tm = 64, 4, 16   # the library's default tiling for D3Q27
     if args.tile:
-        tx, ty, tm = (int(v) for v in args.tile.split(","))
-        sim.set_tiling(tx, ty, tm)
+        sim.set_tiling(*(int(v) for v in args.tile.split(",")))
     sim.init_fields(rho0, u0)
     del rho0, u0
-    print(f"[bench] {w.name}: warmup {args.warmup} steps", file=sys.stderr, flush=True)
+    tuned = 0
+    if not args.tile and not args.no_autotune:
+        # the library's autotuner picks the tiling; its trial steps are steps
+        # of the run, taken before the warm-up and not timed
+        print(f"[bench] {w.name}: autotuning the tiling", file=sys.stderr, flush=True)
+        tuned = sim.autotune(4)
+    tx, ty, tm = sim.get_tiling()
+    print(f"[bench] tiling {tx}x{ty}x{tm}; warmup {args.warmup} steps", file=sys.stderr, flush=True)
     sim.step(args.warmup)
     torch.cuda.synchronize()
 
@@ -277,7 +283,7 @@ def main():
     avg_macro_s = ms_macro / args.steps / 1e3
     achieved = N * b_collide / avg_collide_s / 1e9
     tag = "collide_d3q27_fp32_256"
-    traffic = measured_traffic(tag)
+    traffic = measured_traffic(tag, (tx, ty, tm))
     out = {
         "metric": "MLUPS (D3Q27 FP32 256^3 drop-impact step)",
         "value": round(mlups, 1),
@@ -292,7 +298,8 @@ def main():
         "dtype": "f32",
         "data": "synthetic",
         "config": {"workload": w.name, "lattice": "D3Q27", "grid": list(w.n), "bc": "periodic x,y; walls z",
-                   "collision": "entropic", "density_ratio": 1000},
+                   "collision": "entropic", "density_ratio": 1000, "tiling": [tx, ty, tm],
+                   "autotune_steps": tuned},
         "hbm_gbs_algorithmic_step": round(N * (b_macro + b_collide) / wall * args.steps / 1e9, 1),
         "kernels_ms": {"moments": round(avg_macro_s * 1e3, 4), "collide": round(avg_collide_s * 1e3, 4)},
         "roofline": {

@@ -193,10 +193,14 @@ elmrt_status elmrt_set_stream(elmrt_sim* s, void* stream);
  * wavefronts.  Every tiling gives bitwise the same result. */
 elmrt_status elmrt_set_tiling(elmrt_sim* s, int32_t tx, int32_t ty, int32_t tm);
 
-/* Pick the collision tiling of s by measurement: every compiled tile shape
- * of the lattice with marching depths 1..64 is run for 1 + trial_steps steps
- * (the extra step untimed) and timed with HIP events on the sim's stream;
- * the fastest is kept.  The trial steps advance the simulation (results do
+/* The current tiling (tm = 0: automatic depth); any pointer may be NULL. */
+elmrt_status elmrt_get_tiling(const elmrt_sim* s, int32_t* tx, int32_t* ty, int32_t* tm);
+
+/* Pick the collision tiling of s by measurement, in two stages: every
+ * compiled tile shape of the lattice at marching depths 1, 2, 4, 8, 16, 32,
+ * 64, then the fastest shape at depths 6..62 (even), 96 and 128.  Each
+ * candidate runs 1 + trial_steps steps (the extra step untimed), timed with
+ * HIP events on the sim's stream; the fastest is kept.  The trial steps advance the simulation (results do
  * not depend on the tiling); their number is written to *steps_taken (may be
  * NULL).  Synchronises the stream.  trial_steps >= 1. */
 elmrt_status elmrt_autotune(elmrt_sim* s, int32_t trial_steps, int64_t* steps_taken);
@@ -234,9 +238,10 @@ elmrt_status elmrt_batch_step(elmrt_batch* b, int64_t nsteps);
  * captured graph (same results). */
 elmrt_status elmrt_batch_set_graph(elmrt_batch* b, int32_t use_graph);
 
-/* Pick one collision tiling for all members by measurement (as
- * elmrt_autotune, over the batch: each candidate runs 2 + trial_steps batch
- * steps, the marching depth capped at each member's last extent).  The
+/* Pick one collision tiling for all members by measurement: every compiled
+ * tile shape at depths 1, 2, 4, 8, 16, 32, 64 (the first stage of
+ * elmrt_autotune); each candidate runs 2 + trial_steps batch steps, the
+ * marching depth capped at each member's last extent.  The
  * trial steps advance every member; their number goes to *steps_taken. */
 elmrt_status elmrt_batch_autotune(elmrt_batch* b, int32_t trial_steps, int64_t* steps_taken);
 

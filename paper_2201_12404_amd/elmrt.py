@@ -67,6 +67,8 @@ _SIGS = {
     "elmrt_pressure": (ctypes.c_int, [ctypes.POINTER(elmrt_params), _dp, _dp, ctypes.c_int64]),
     "elmrt_set_tiling": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_int32, ctypes.c_int32, ctypes.c_int32]),
     "elmrt_set_stream": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p]),
+    "elmrt_get_tiling": (ctypes.c_int, [ctypes.c_void_p, ctypes.POINTER(ctypes.c_int32),
+                                        ctypes.POINTER(ctypes.c_int32), ctypes.POINTER(ctypes.c_int32)]),
     "elmrt_gamma_fallbacks": (ctypes.c_int, [ctypes.c_void_p, ctypes.POINTER(ctypes.c_int64)]),
     "elmrt_state_bytes": (ctypes.c_int, [ctypes.c_void_p, ctypes.POINTER(ctypes.c_size_t)]),
     "elmrt_poll_unstable": (ctypes.c_int, [ctypes.c_void_p, ctypes.POINTER(ctypes.c_uint32)]),
@@ -311,6 +313,12 @@ def elmrt_gamma_fallbacks(sim: int) -> int:
     return out.value
 
 
+def elmrt_get_tiling(sim: int):
+    tx, ty, tm = ctypes.c_int32(), ctypes.c_int32(), ctypes.c_int32()
+    _check(lib().elmrt_get_tiling(ctypes.c_void_p(sim), ctypes.byref(tx), ctypes.byref(ty), ctypes.byref(tm)))
+    return tx.value, ty.value, tm.value
+
+
 def elmrt_set_stream(sim: int, stream_ptr: int) -> None:
     _check(lib().elmrt_set_stream(ctypes.c_void_p(sim), ctypes.c_void_p(stream_ptr)))
 
@@ -486,6 +494,9 @@ class Simulation:
 
     def set_tiling(self, tx, ty, tm):
         elmrt_set_tiling(self.handle, tx, ty, tm)
+
+    def get_tiling(self):
+        return elmrt_get_tiling(self.handle)
 
     def set_stream(self, stream):
         """Enqueue later calls on ``stream`` (a torch.cuda.Stream); work
