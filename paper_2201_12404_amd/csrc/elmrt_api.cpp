@@ -802,7 +802,7 @@ elmrt_status batch_build(elmrt_batch* b)
         J.flag = s->flag;
         J.g = s->L.g;
         J.ph = s->ph;
-        const elmrt::Tiling mt = elmrt::macro_tiling(s->D, s->L.g, false);
+        const elmrt::Tiling mt = elmrt::macro_tiling(s->D, s->L.g);
         const int tm = member_depth(s, cap);
         const elmrt::Tiling ct = elmrt::collide_tiling(s->D, s->L.g, s->tx, s->ty, tm);
         J.mbx = mt.bx;

@@ -99,9 +99,7 @@ struct Tiling {
     int bx, by, bm, tm;   // tiles along x, y, the marching axis; planes per tile
     long long blocks;
 };
-// alone: the launch covers one grid, so a small grid shortens the march to
-// spread its rows over more workgroups; batched launches keep the full march.
-Tiling macro_tiling(int D, const Grid& g, bool alone);
+Tiling macro_tiling(int D, const Grid& g);
 Tiling collide_tiling(int D, const Grid& g, int tx, int ty, int tm);
 constexpr int kMacroTX = 256;
 
