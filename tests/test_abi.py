@@ -146,3 +146,31 @@ def test_server_create_rejects_bad_arguments_without_a_device():
         E.elmrt_server_create(0, 1 << 20, 0, 10)
     with pytest.raises(E.ElmrtError, match="chunk"):
         E.elmrt_server_create(256, 1 << 20, 0, 0)
+
+
+def test_null_handles_rejected_without_a_device():
+    """Every entry point that takes a handle refuses NULL with
+    ELMRT_E_INVALID before touching the device."""
+    L = E.lib()
+    null = ctypes.c_void_p(0)
+    i64, i32, sz, u32 = ctypes.c_int64(), ctypes.c_int32(), ctypes.c_size_t(), ctypes.c_uint32()
+    d = np.zeros(4)
+    calls = {
+        "elmrt_step": lambda: L.elmrt_step(null, 1),
+        "elmrt_set_tiling": lambda: L.elmrt_set_tiling(null, 64, 1, 0),
+        "elmrt_get_tiling": lambda: L.elmrt_get_tiling(null, None, None, None),
+        "elmrt_set_stream": lambda: L.elmrt_set_stream(null, null),
+        "elmrt_autotune": lambda: L.elmrt_autotune(null, 2, ctypes.byref(i64)),
+        "elmrt_gamma_fallbacks": lambda: L.elmrt_gamma_fallbacks(null, ctypes.byref(i64)),
+        "elmrt_poll_unstable": lambda: L.elmrt_poll_unstable(null, ctypes.byref(u32)),
+        "elmrt_state_bytes": lambda: L.elmrt_state_bytes(null, ctypes.byref(sz)),
+        "elmrt_save_state": lambda: L.elmrt_save_state(null, null, 0),
+        "elmrt_load_state": lambda: L.elmrt_load_state(null, null, 0),
+        "elmrt_read_macros": lambda: L.elmrt_read_macros(null, None, None, None),
+        "elmrt_batch_step": lambda: L.elmrt_batch_step(null, 1),
+        "elmrt_batch_autotune": lambda: L.elmrt_batch_autotune(null, 2, ctypes.byref(i64)),
+        "elmrt_server_run": lambda: L.elmrt_server_run(null, 1, ctypes.byref(i32), ctypes.byref(i32)),
+        "elmrt_server_stats": lambda: L.elmrt_server_stats(null, ctypes.byref(i64), ctypes.byref(sz)),
+    }
+    for name, call in calls.items():
+        assert call() == E.ELMRT_E_INVALID, name
