@@ -759,7 +759,8 @@ __device__ __forceinline__ void collide_tile(int b, const T* __restrict__ cur, T
     constexpr int NT = TX * TY;
     constexpr int NE = (HX * HY + NT - 1) / NT;   // halo entries staged per thread and plane
     constexpr int MA = D - 1;
-    __shared__ V2<double> tile[5][HY][HX];   // rho and signed psi, FP64
+    __shared__ double tpsi[5][HY][HX];   // signed psi, FP64
+    __shared__ T trho[5][HY][HX];        // rho as stored (exact in FP64)
 
     const TileCoords t = tile_of<D, TX, TY>(g, b, bx, by, tm);
     const int tx = threadIdx.x;
@@ -795,10 +796,8 @@ __device__ __forceinline__ void collide_tile(int b, const T* __restrict__ cur, T
         for (int k = 0; k < NE; ++k) {
             if (hoff[k] >= 0) {
                 const int e = lid + k * NT;
-                V2<double> v;
-                v.rho = (double)r[k];
-                v.psi = psi_signed<double>(v.rho, ph);
-                (&tile[slot][0][0])[e] = v;
+                (&tpsi[slot][0][0])[e] = psi_signed<double>((double)r[k], ph);
+                (&trho[slot][0][0])[e] = r[k];
             }
         }
     };
@@ -872,7 +871,7 @@ __device__ __forceinline__ void collide_tile(int b, const T* __restrict__ cur, T
 #pragma unroll
             for (int d = 0; d < 5; ++d) sl[d] = (m - t.m0 + d) % 5;   // plane m + d - 2
             const int hy0 = (D == 3) ? ty + 2 : 0;
-            const V2<double> c0 = tile[sl[2]][hy0][tx + 2];
+            const double c0psi = tpsi[sl[2]][hy0][tx + 2];
             // force stencils (Sec. 2.3): sums of 3 w_i c_i times
             // [4/3 psi(r+c_i) - 1/6 psi(r+2c_i)] and [rho(r+2c_i) - 2 rho(r+c_i)],
             // taken over the pairs (c, -c) so that each pair costs one
@@ -887,16 +886,22 @@ __device__ __forceinline__ void collide_tile(int b, const T* __restrict__ cur, T
                 const double w = (k == 1) ? ((D == 3) ? 2.0 / 9.0 : 1.0 / 3.0)
                                           : (k == 2) ? ((D == 3) ? 1.0 / 18.0 : 1.0 / 12.0) : 1.0 / 72.0;
                 V2<double> p1, p2, m1, m2;
+                auto at = [&](int d, int oy, int ox) {
+                    V2<double> v;
+                    v.psi = tpsi[sl[d]][oy][ox];
+                    v.rho = (double)trho[sl[d]][oy][ox];
+                    return v;
+                };
                 if (D == 3) {
-                    p1 = tile[sl[2 + cz]][hy0 + cy][tx + 2 + cx];
-                    p2 = tile[sl[2 + 2 * cz]][hy0 + 2 * cy][tx + 2 + 2 * cx];
-                    m1 = tile[sl[2 - cz]][hy0 - cy][tx + 2 - cx];
-                    m2 = tile[sl[2 - 2 * cz]][hy0 - 2 * cy][tx + 2 - 2 * cx];
+                    p1 = at(2 + cz, hy0 + cy, tx + 2 + cx);
+                    p2 = at(2 + 2 * cz, hy0 + 2 * cy, tx + 2 + 2 * cx);
+                    m1 = at(2 - cz, hy0 - cy, tx + 2 - cx);
+                    m2 = at(2 - 2 * cz, hy0 - 2 * cy, tx + 2 - 2 * cx);
                 } else {
-                    p1 = tile[sl[2 + cy]][0][tx + 2 + cx];
-                    p2 = tile[sl[2 + 2 * cy]][0][tx + 2 + 2 * cx];
-                    m1 = tile[sl[2 - cy]][0][tx + 2 - cx];
-                    m2 = tile[sl[2 - 2 * cy]][0][tx + 2 - 2 * cx];
+                    p1 = at(2 + cy, 0, tx + 2 + cx);
+                    p2 = at(2 + 2 * cy, 0, tx + 2 + 2 * cx);
+                    m1 = at(2 - cy, 0, tx + 2 - cx);
+                    m2 = at(2 - 2 * cy, 0, tx + 2 - 2 * cx);
                 }
                 const double tt = (w * (4.0 / 3.0)) * (fabs(p1.psi) - fabs(m1.psi)) - (w * (1.0 / 6.0)) * (fabs(p2.psi) - fabs(m2.psi));
                 const double kk = w * (p2.rho - m2.rho) - (2.0 * w) * (p1.rho - m1.rho);
@@ -923,7 +928,7 @@ __device__ __forceinline__ void collide_tile(int b, const T* __restrict__ cur, T
             const double half_rate = (1.0 - 0.5 * omega) * 0.5;
 #pragma unroll
             for (int a = 0; a < D; ++a) {
-                F[a] = 2.0 * (double)c0.psi * G[a] + ph.kappa * rhoc * K[a];
+                F[a] = 2.0 * c0psi * G[a] + ph.kappa * rhoc * K[a];
                 Phi[a] = half_rate * dq[a];
             }
             const bool fell_back = collide<D, T, double>(f, rhoc, j, F, Phi, omega, ph.entropic);
