@@ -257,6 +257,7 @@ def main():
     if not args.autotune:
         sim.set_tiling(*(int(v) for v in args.tile.split(",")))
     sim.init_fields(rho0, u0)
+    mass0 = float(rho0.sum())
     del rho0, u0
     tuned = 0
     if args.autotune:
@@ -274,7 +275,10 @@ def main():
     ms_macro, ms_collide = sim.step_timed(args.steps)
     torch.cuda.synchronize()
     wall = time.perf_counter() - t0
-    _, _, sums = sim.read_macros()
+    _, u_end, sums = sim.read_macros()
+    fallbacks = sim.gamma_fallbacks()
+    umax = float(np.sqrt((u_end ** 2).sum(axis=0)).max())
+    del u_end
     sim.close()
 
     N = w.N
@@ -315,7 +319,8 @@ def main():
             "traffic": traffic,
             "bytes_per_cell": b_collide,
         },
-        "mass_sum": sums[0],
+        "diagnostics": {"mass_drift": sums[0] / mass0 - 1.0, "gamma_fallbacks": fallbacks,
+                        "max_speed": round(umax, 6), "steps_run": args.warmup + args.steps + tuned},
     }
     if args.copy_probe:
         copy_probe()

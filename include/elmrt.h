@@ -198,7 +198,8 @@ elmrt_status elmrt_get_tiling(const elmrt_sim* s, int32_t* tx, int32_t* ty, int3
 
 /* Pick the collision tiling of s by measurement, in two stages: every
  * compiled tile shape of the lattice at marching depths 1, 2, 4, 8, 16, 32,
- * 64, then the fastest shape at depths 6..62 (even), 96 and 128.  Each
+ * 64, then the fastest shape at depths 6..62 (even), 96 and 128; the three
+ * fastest candidates are then timed again over 3 x trial_steps.  Each
  * candidate runs 1 + trial_steps steps (the extra step untimed), timed with
  * HIP events on the sim's stream; the fastest is kept.  The trial steps advance the simulation (results do
  * not depend on the tiling); their number is written to *steps_taken (may be

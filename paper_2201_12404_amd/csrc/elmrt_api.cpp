@@ -697,33 +697,40 @@ elmrt_status elmrt_autotune(elmrt_sim* s, int32_t trial_steps, int64_t* steps_ta
     if (trial_steps < 1) return fail(ELMRT_E_INVALID, "trial_steps must be >= 1");
     if (!s->initialised) return fail(ELMRT_E_STATE, "elmrt_init_fields has not been called");
     int64_t taken = 0;
-    float best = 0.f;
-    std::array<int, 3> arg{s->tx, s->ty, s->tm};
-    auto trial = [&](const std::array<int, 3>& c) -> elmrt_status {
+    std::vector<std::pair<float, std::array<int, 3>>> timed;
+    auto trial = [&](const std::array<int, 3>& c, int steps, float* ms) -> elmrt_status {
         s->tx = c[0];
         s->ty = c[1];
         s->tm = c[2];
-        float ms = 0.f;
         elmrt_status st = step_impl(s, 1, nullptr);   // first launch of a shape: not timed
-        if (st == ELMRT_OK) st = time_steps(s->stream, [&] { return step_impl(s, trial_steps, nullptr); }, &ms);
-        if (st != ELMRT_OK) return st;
-        taken += 1 + trial_steps;
-        if (best == 0.f || ms < best) {
-            best = ms;
-            arg = c;
-        }
-        return ELMRT_OK;
+        if (st == ELMRT_OK) st = time_steps(s->stream, [&] { return step_impl(s, steps, nullptr); }, ms);
+        if (st == ELMRT_OK) taken += 1 + steps;
+        return st;
+    };
+    auto best_of = [&]() {
+        return std::min_element(timed.begin(), timed.end(),
+                                [](const auto& x, const auto& y) { return x.first < y.first; })->second;
     };
     // stage 1: every shape at the coarse depths; stage 2: the best shape at
-    // the fine depths
+    // the fine depths; stage 3: the three fastest again, three times longer
     elmrt_status st = ELMRT_OK;
-    for (const auto& c : tiling_candidates(s->D))
-        if ((st = trial(c)) != ELMRT_OK) return st;
-    const std::array<int, 3> shape = arg;
+    float ms = 0.f;
+    for (const auto& c : tiling_candidates(s->D)) {
+        if ((st = trial(c, trial_steps, &ms)) != ELMRT_OK) return st;
+        timed.push_back({ms, c});
+    }
+    const std::array<int, 3> shape = best_of();
     for (int tm : fine_depths()) {
         if (std::find(coarse_depths().begin(), coarse_depths().end(), tm) != coarse_depths().end()) continue;
-        if ((st = trial({shape[0], shape[1], tm})) != ELMRT_OK) return st;
+        const std::array<int, 3> c{shape[0], shape[1], tm};
+        if ((st = trial(c, trial_steps, &ms)) != ELMRT_OK) return st;
+        timed.push_back({ms, c});
     }
+    std::sort(timed.begin(), timed.end(), [](const auto& x, const auto& y) { return x.first < y.first; });
+    timed.resize(std::min<size_t>(3, timed.size()));
+    for (auto& t : timed)
+        if ((st = trial(t.second, 3 * trial_steps, &t.first)) != ELMRT_OK) return st;
+    const std::array<int, 3> arg = best_of();
     s->tx = arg[0];
     s->ty = arg[1];
     s->tm = arg[2];
