@@ -294,7 +294,8 @@ elmrt_status elmrt_server_create(void* dev_pool, size_t pool_bytes, void* stream
 elmrt_status elmrt_server_set_fill(elmrt_server* s, int64_t cells);
 
 /* Scheduling order of resident jobs: 0 arrival, 1 least remaining work
- * (cells x remaining steps) first. */
+ * (cells x remaining steps) first, 2 as 1 but the oldest resident job always
+ * first (it advances every round, so none starves). */
 elmrt_status elmrt_server_set_policy(elmrt_server* s, int32_t policy);
 
 /* Queue a job; the fields (rho0[N], u0[D][N], FP64 host) are copied.  Fails

@@ -135,7 +135,8 @@ struct elmrt_server {
     std::vector<int> free_slots;
     int64_t chunk = 100;
     int64_t fill = 4 << 20;             // cells advanced per round (at least one job)
-    int32_t policy = 1;                 // 0 arrival order, 1 shortest remaining work first
+    int32_t policy = 1;                 // 0 arrival order, 1 shortest remaining work first,
+                                        // 2 as 1 with the oldest job in every round
     int64_t next_id = 1;
     std::deque<Job*> queue;
     std::vector<Job*> resident;
@@ -259,10 +260,17 @@ elmrt_status round_once(elmrt_server* s)
     std::vector<Job*> order;
     for (Job* j : s->resident)
         if (j->done < j->steps && !j->unstable) order.push_back(j);
-    if (s->policy == 1)
+    if (s->policy >= 1) {
+        // resident is in arrival order: its first runnable job is the oldest
+        Job* oldest = order.empty() ? nullptr : order.front();
         std::stable_sort(order.begin(), order.end(), [](const Job* a, const Job* b) {
             return (double)a->N * (double)(a->steps - a->done) < (double)b->N * (double)(b->steps - b->done);
         });
+        if (s->policy == 2 && oldest) {   // the oldest first: it cannot starve
+            order.erase(std::find(order.begin(), order.end(), oldest));
+            order.insert(order.begin(), oldest);
+        }
+    }
     std::vector<Job*> running;
     int64_t cells = 0;
     for (Job* j : order) {
@@ -355,7 +363,7 @@ elmrt_status elmrt_server_set_fill(elmrt_server* s, int64_t cells)
 elmrt_status elmrt_server_set_policy(elmrt_server* s, int32_t policy)
 {
     if (!s) return sfail(ELMRT_E_INVALID, "server is NULL");
-    if (policy != 0 && policy != 1) return sfail(ELMRT_E_INVALID, "policy must be 0 or 1");
+    if (policy < 0 || policy > 2) return sfail(ELMRT_E_INVALID, "policy must be 0, 1 or 2");
     s->policy = policy;
     return ELMRT_OK;
 }

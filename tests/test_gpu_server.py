@@ -104,11 +104,11 @@ def test_server_rejects_invalid_job():
     srv.close()
 
 
-@pytest.mark.parametrize("policy", [0, 1])
+@pytest.mark.parametrize("policy", [0, 1, 2])
 def test_fill_budget_takes_turns(policy):
     """With a fill budget of one cell only one resident job advances in a
-    round: the oldest (policy 0) or the one with the least remaining work,
-    cells x steps (policy 1); the other starts when it is done, and both
+    round: the oldest (policies 0 and 2) or the one with the least remaining
+    work, cells x steps (policy 1); the other starts when it is done, and both
     results are those of the jobs run alone."""
     w1, w2 = W.impact_job(2, 128, 1000, 0.05, 12, 0), W.impact_job(2, 96, 10, 0.03, 8, 1)
     srv = E.Server(pool_bytes=1 << 28, chunk_steps=4)
@@ -117,7 +117,7 @@ def test_fill_budget_takes_turns(policy):
     a = srv.submit(E.params_for(w1), *W.initial_fields(w1), 12)
     b = srv.submit(E.params_for(w2), *W.initial_fields(w2), 8)
     srv.run(2)          # the first round admits both, the second advances one
-    first, second = (a, b) if policy == 0 else (b, a)
+    first, second = (a, b) if policy in (0, 2) else (b, a)
     assert srv.job(first)[2] == 4 and srv.job(second)[2] == 0
     while srv.run(1) != (0, 0):
         pass
