@@ -820,9 +820,10 @@ elmrt_status batch_build(elmrt_batch* b)
         J.ctm = tm;
         J.mfirst = (int)mfirst;
         J.cfirst = (int)cfirst;
+        J.cblocks = (int)ct.blocks;
         J.cur0 = s->cur;
         mfirst += mt.blocks;
-        cfirst += ct.blocks;
+        cfirst += (ct.blocks + 7) / 8 * 8;   // ranges start on multiples of 8 (one per XCD)
         b->groups.back().count += 1;
         b->groups.back().blocks = cfirst;
         if (mfirst > 0x7fffffffLL || cfirst > 0x7fffffffLL) return fail(ELMRT_E_INVALID, "batch has >= 2^31 tiles");

@@ -51,9 +51,9 @@ struct BatchJob {
     Phys<double> ph;
     int mbx, mby, mtm;    // moment-pass tiling
     int cbx, cby, ctm;    // collision tiling
-    int mfirst, cfirst;   // first workgroup of this job in each launch
+    int mfirst, cfirst;   // first workgroup of this job in each launch (cfirst: a multiple of 8)
     int cur0;             // buffer holding f at batch parity 0
-    int pad;
+    int cblocks;          // collision workgroups of this job (its range is padded to a multiple of 8)
 };
 
 // Every launcher returns the launch status (hipGetLastError after the launch).

@@ -948,6 +948,19 @@ __device__ __forceinline__ void collide_tile(int b, const T* __restrict__ cur, T
     }
 }
 
+// Tile of workgroup b (of nb, bx x-tiles per row) such that the x-tiles of a
+// row run on one XCD in consecutive slots: workgroup b runs on XCD b % 8, so
+// slot s = b / 8 of XCD j takes x-tile s % bx of row 8 (s / bx) + j.  The
+// boundary cache lines that neighbouring x-tiles share are then fetched into
+// one L2.  Rows beyond the last full group of 8 keep the natural order.
+__device__ __forceinline__ int row_xcd_order(int b, int nb, int bx)
+{
+    const int full = ((nb / bx) >> 3) << 3;
+    if (b >= bx * full) return b;
+    const int s = b >> 3, j = b & 7;
+    return (s % bx) + bx * (((s / bx) << 3) + j);
+}
+
 // Single-simulation entry points: one workgroup per tile.
 template <int D, typename T, int TX, int TY>
 __global__ __launch_bounds__(TX* TY) void k_macro(const T* __restrict__ cur, T* __restrict__ rho_out,
@@ -962,7 +975,8 @@ __global__ __launch_bounds__(TX* TY) __attribute__((amdgpu_waves_per_eu(CollideW
     const T* __restrict__ cur, T* __restrict__ nxt, const T* __restrict__ rho, const T* __restrict__ q, Grid g,
     Phys<double> ph, int bx, int by, int tm, unsigned long long* __restrict__ fallbacks)
 {
-    collide_tile<D, T, TX, TY>((int)blockIdx.x, cur, nxt, rho, q, g, ph, bx, by, tm, fallbacks);
+    collide_tile<D, T, TX, TY>(row_xcd_order((int)blockIdx.x, (int)gridDim.x, bx), cur, nxt, rho, q, g, ph, bx, by,
+                               tm, fallbacks);
 }
 
 // Batched entry points: the workgroups of one launch cover the tiles of every
@@ -997,7 +1011,10 @@ __global__ __launch_bounds__(TX* TY) __attribute__((amdgpu_waves_per_eu(CollideW
     const int b = (int)blockIdx.x;
     const int j = job_of(jobs, njobs, b, &BatchJob::cfirst);
     const BatchJob& J = jobs[j];
-    collide_tile<D, T, TX, TY>(b - J.cfirst, (const T*)J.buf[J.cur0 ^ parity], (T*)J.buf[J.cur0 ^ parity ^ 1],
+    const int lb = b - J.cfirst;   // J.cfirst is a multiple of 8: lb % 8 is the XCD
+    if (lb >= J.cblocks) return;   // padding up to the next job
+    collide_tile<D, T, TX, TY>(row_xcd_order(lb, J.cblocks, J.cbx), (const T*)J.buf[J.cur0 ^ parity],
+                               (T*)J.buf[J.cur0 ^ parity ^ 1],
                                (const T*)J.rho, (const T*)J.q, J.g, J.ph, J.cbx, J.cby, J.ctm,
                                gamma_fallbacks(J.flag));
 }
