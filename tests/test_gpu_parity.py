@@ -219,13 +219,15 @@ def test_minimal_grid():
 
 
 def test_full_size_3d_one_step_sampled():
-    """256^3 D3Q27 FP32 impact in the benchmark's launch configuration: one
-    step from the seeded state, sampled cells against the oracle's
-    single-cell update (including wall-adjacent and periodic-seam cells)."""
+    """256^3 D3Q27 FP32 impact in the benchmark's launch configuration (64 x 4
+    tiles marching 46 planes): one step from the seeded state, sampled cells
+    against the oracle's single-cell update (including wall-adjacent and
+    periodic-seam cells)."""
     w = W.IMPACT_3D
     rho0, u0 = W.initial_fields(w)
     say("[gpu] full-size 256^3 one step")
     sim = E.Simulation(E.params_for(w))
+    sim.set_tiling(64, 4, 46)
     sim.init_fields(rho0, u0)
     sim.step(1)
     f_g = sim.read_populations()
@@ -250,6 +252,35 @@ def test_full_size_3d_one_step_sampled():
     # mass of the whole grid: FP64 sums of the FP32 state
     m0 = rho0.sum()
     assert abs(sums[0] / m0 - 1) < 1e-6
+
+
+def test_full_size_2d_sampled():
+    """1024 x 512 D2Q9 FP32 impact at full size with the library's default
+    tiling: one step from the seeded state, sampled cells (walls, periodic
+    seam, interfaces, drop) against the oracle's single-cell update."""
+    w = W.IMPACT_2D
+    rho0, u0 = W.initial_fields(w)
+    say("[gpu] full-size 1024x512 one step")
+    sim = E.Simulation(E.params_for(w))
+    sim.init_fields(rho0, u0)
+    sim.step(1)
+    f_g = sim.read_populations()
+    sim.close()
+    n = w.n
+    rng = np.random.default_rng(12)
+    pts = [(0, 0), (1023, 511), (0, 511), (1023, 0), (512, 16), (512, 17), (512, 110), (430, 30), (600, 100)]
+    pts += [tuple(int(v) for v in (rng.integers(0, n[0]), rng.integers(0, n[1]))) for _ in range(40)]
+    pts += [(int(x), int(y)) for x, y in zip(rng.integers(400, 624, 30), rng.integers(5, 200, 30))]
+    cells = np.array([x + n[0] * y for x, y in pts])
+    p = oracle_params(w)
+    f0 = O.init_fluid(p, rho0, u0)
+    f_o = O.update_cells(p, f0, cells)
+    m = velocity_map(E.elmrt_velocities(w.lattice), 2)
+    ref = f_o[:, m]
+    got = f_g[:, cells].T
+    err = np.abs(got - ref).max() / np.abs(ref).max()
+    say(f"full-size 2-D one step sampled: max rel err {err:.3e}")
+    assert err < 1e-6
 
 
 def test_unstable_flag_is_reported():
