@@ -161,22 +161,28 @@ def served_vs_plain(count: int, step_scale: float, pool_gib: float = 16.0, chunk
     # plain: service times of each job alone
     service = []
     inputs = [W.initial_fields(w) for _, w, _ in jobs]
-    for (_, w, n), (rho0, u0) in zip(jobs, inputs):
+    unstable = []
+    for k, ((_, w, n), (rho0, u0)) in enumerate(zip(jobs, inputs)):
         sim = E.Simulation(E.params_for(w))
         torch.cuda.synchronize()
         t0 = time.perf_counter()
         sim.init_fields(rho0, u0)
         sim.step(n)
-        sim.read_macros()
+        try:
+            sim.read_macros()
+        except E.ElmrtUnstable:
+            unstable.append(k)   # run to its step count, like the others
         service.append(time.perf_counter() - t0)
         sim.close()
+        if k % 20 == 19:
+            print(f"[bench] plain: {k + 1} of {len(jobs)} jobs", file=sys.stderr, flush=True)
     finish, lat = 0.0, []
     for (t, _, _), sv in zip(jobs, service):
         finish = max(finish, t) + sv
         lat.append(finish - t)
     plain = {"p50_s": round(float(np.percentile(lat, 50)), 3), "p99_s": round(float(np.percentile(lat, 99)), 3),
              "mlups": round(lu_total / finish / 1e6, 1), "makespan_s": round(finish, 3),
-             "busy_s": round(sum(service), 3)}
+             "busy_s": round(sum(service), 3), "unstable_jobs": unstable}
 
     # served: real-time replay of the arrivals
     srv = E.Server(pool_bytes=int(pool_gib * (1 << 30)), chunk_steps=chunk)
@@ -185,6 +191,7 @@ def served_vs_plain(count: int, step_scale: float, pool_gib: float = 16.0, chunk
     ids = [None] * len(jobs)
     t_start = time.monotonic()
     k = 0
+    last = t_start
     while True:
         now = time.monotonic() - t_start
         while k < len(jobs) and jobs[k][0] <= now:
@@ -192,18 +199,23 @@ def served_vs_plain(count: int, step_scale: float, pool_gib: float = 16.0, chunk
             ids[k] = srv.submit(E.params_for(w), inputs[k][0], inputs[k][1], n)
             k += 1
         q, r = srv.run(1)
+        if time.monotonic() - last > 10.0:
+            last = time.monotonic()
+            print(f"[bench] served: {k} submitted, {q} queued, {r} resident", file=sys.stderr, flush=True)
         if k == len(jobs) and q == 0 and r == 0:
             break
         if q == 0 and r == 0 and k < len(jobs):
             time.sleep(max(0.0, min(0.01, jobs[k][0] - (time.monotonic() - t_start))))
     t_end = time.monotonic() - t_start
-    lat_s = []
-    for (t, _, _), jid in zip(jobs, ids):
-        st, times, _ = srv.job(jid)
+    lat_s, evicted = [], []
+    for k, ((t, _, n), jid) in enumerate(zip(jobs, ids)):
+        st, times, done = srv.job(jid)
         lat_s.append(times[2] - (t_start + t))
+        if done < n:
+            evicted.append(k)   # went unstable: read out early
     srv.close()
     served = {"p50_s": round(float(np.percentile(lat_s, 50)), 3), "p99_s": round(float(np.percentile(lat_s, 99)), 3),
-              "mlups": round(lu_total / t_end / 1e6, 1), "makespan_s": round(t_end, 3)}
+              "mlups": round(lu_total / t_end / 1e6, 1), "makespan_s": round(t_end, 3), "evicted_jobs": evicted}
     return {"workload": f"first {count} jobs of the served stream (seed 0, 20 jobs/s), steps x {step_scale}, "
                         f"{lu_total:.3e} lattice updates, FP32",
             "served": served, "plain": plain,
