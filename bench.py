@@ -24,6 +24,30 @@ sys.path.insert(0, ROOT)
 HBM_PEAK_GBS = 8000.0
 
 
+class _Ranges:
+    """roctx ranges around the benchmark's phases (visible with rocprofv3
+    --marker-trace); no-ops where the roctx library is absent."""
+
+    def __init__(self):
+        import ctypes
+        self._lib = None
+        for name in ("librocprofiler-sdk-roctx.so.1", "librocprofiler-sdk-roctx.so"):
+            try:
+                self._lib = ctypes.CDLL(name)
+                self._lib.roctxRangePushA.argtypes = [ctypes.c_char_p]
+                break
+            except (OSError, AttributeError):
+                self._lib = None
+
+    def push(self, name: str):
+        if self._lib:
+            self._lib.roctxRangePushA(name.encode())
+
+    def pop(self):
+        if self._lib:
+            self._lib.roctxRangePop()
+
+
 def kernel_source_hash() -> str:
     h = hashlib.sha256()
     for fn in ("elmrt_kernels.hip", "elmrt_internal.h"):
@@ -279,14 +303,19 @@ def main():
         tuned = sim.autotune(4)
     tx, ty, tm = sim.get_tiling()
     print(f"[bench] tiling {tx}x{ty}x{tm}; warmup {args.warmup} steps", file=sys.stderr, flush=True)
+    ranges = _Ranges()
+    ranges.push("warmup")
     sim.step(args.warmup)
     torch.cuda.synchronize()
 
+    ranges.pop()
     print(f"[bench] timing {args.steps} steps", file=sys.stderr, flush=True)
+    ranges.push("timed steps")
     t0 = time.perf_counter()
     ms_macro, ms_collide = sim.step_timed(args.steps)
     torch.cuda.synchronize()
     wall = time.perf_counter() - t0
+    ranges.pop()
     _, u_end, sums = sim.read_macros()
     fallbacks = sim.gamma_fallbacks()
     umax = float(np.sqrt((u_end ** 2).sum(axis=0)).max())
@@ -338,9 +367,13 @@ def main():
         copy_probe()
     if not args.no_batched:
         print("[bench] batched vs plain (64 static drops)", file=sys.stderr, flush=True)
+        ranges.push("batched vs plain")
         out["batched"] = batched_vs_plain()
+        ranges.pop()
         print("[bench] served vs plain", file=sys.stderr, flush=True)
+        ranges.push("served vs plain")
         out["served"] = served_vs_plain(args.serve_jobs, args.serve_step_scale)
+        ranges.pop()
     if not args.no_cpu_baseline:
         print("[bench] cpu baseline", file=sys.stderr, flush=True)
         out["cpu_baseline"] = cpu_baseline(w, args.cpu_budget)
