@@ -154,3 +154,18 @@ def test_crown_diameter_grows_3d():
     assert np.all(np.diff(h["r_R0"]) > 0)
     assert 0.25 < n < 0.7
     assert res < 0.03 and tc < 0.05
+
+
+def test_stability_domain_bgk_vs_entropic():
+    """2-D drop impacts (R0 = 50, W = 5, density ratio 1000, 3000 steps):
+    at nu = 0.005 the BGK collision diverges where the entropic one holds,
+    and both hold at nu = 0.04 (Sec. 3.2: the entropic stability domain
+    extends to much lower viscosity)."""
+    nus, u0s = [0.005, 0.04], [0.02, 0.05]
+    runs, _ = S.stability_map(nus, u0s, steps=3000)
+    table = {(r.collision, r.workload.nu_liquid, r.workload.u_impact): r.stable for r in runs}
+    say("stability " + str(sorted(table.items())))
+    for u0 in u0s:
+        assert not table[(E.ELMRT_BGK, 0.005, u0)]
+        assert table[(E.ELMRT_ENTROPIC, 0.005, u0)]
+        assert table[(E.ELMRT_BGK, 0.04, u0)] and table[(E.ELMRT_ENTROPIC, 0.04, u0)]
