@@ -155,12 +155,14 @@ def slab(tr: float, a: float = 0.003, n=(800, 10), half: float = 200.0, width: f
 
 
 def laplace_drop(tr: float, R: float, a: float = 0.003, width: float = 5.0, nu: float = 0.1,
-                 precision: int = 0) -> W.Workload:
-    """Resting drop of radius R in a periodic square box of side 4R + 20W."""
+                 precision: int = 0, kappa: float | None = None) -> W.Workload:
+    """Resting drop of radius R in a periodic square box of side 4R + 20W;
+    kappa~ = kappa_for(tr, a) (interface width ~5 at every T) unless given."""
     rv, rl = _coex(tr, a)
     N = int(4 * R + 20 * width)
+    k = kappa_for(tr, a) if kappa is None else kappa
     return W.Workload(name=f"laplace-{tr}-{R}-{a}", lattice=0, n=(N, N), bc=(0, 0), precision=precision, eos=_eos(a),
-                      T_over_Tc=tr, kappa_tilde=kappa_for(tr, a), nu_liquid=nu, nu_vapour=nu, rho_v=rv, rho_l=rl,
+                      T_over_Tc=tr, kappa_tilde=k, nu_liquid=nu, nu_vapour=nu, rho_v=rv, rho_l=rl,
                       kind="drop", radius=R, width=width, centre=((N - 1) / 2, (N - 1) / 2))
 
 
@@ -181,7 +183,7 @@ def _converge(workloads, steps_max: int, chunk: int, tol: float):
         b.step(chunk)
         done += chunk
         for k, sim in enumerate(sims):
-            rho, _, _ = sim.read_macros()
+            rho = sim.read_density()
             if prev[k] is not None and np.abs(rho - prev[k]).max() < tol * np.abs(rho).max():
                 conv[k] = True
             prev[k] = rho
@@ -233,6 +235,43 @@ def laplace_sweep(temps, radii, a: float = 0.003, steps_max: int = 40000, chunk:
         out.append(dict(T_over_Tc=w.T_over_Tc, a=a, R0=w.radius, rho_in=r_in, rho_out=r_out, dP=dP, R_e=Re,
                         sigma=dP * Re, steps=steps, converged=ok))
     return out
+
+
+def surface_tension_map(temps, avals, R: float = 40.0, kappa_at: float | None = None, **kw) -> dict:
+    """Laplace-law surface tension against T/Tc for several attraction
+    parameters a of the Peng-Robinson EOS (b = 0.095; Sec. 3.1.2):
+    {a: laplace_sweep records}.  kappa~ scales with a; by default it also
+    varies with T to keep the interface width ~5, with kappa_at = T/Tc it is
+    held at its value there for every T (the width then grows towards Tc)."""
+    out = {}
+    for a in avals:
+        if kappa_at is None:
+            out[a] = laplace_sweep(temps, [R], a=a, **kw)
+        else:
+            out[a] = laplace_sweep(temps, [R], a=a, kappa=kappa_for(kappa_at, a), **kw)
+    return out
+
+
+def drop_a(tr: float, a: float, nu: float, kappa: float, N: int = 128, R: float = 25.0,
+           width: float = 5.0) -> W.Workload:
+    """Resting drop of the Peng-Robinson EOS with attraction a (b = 0.095) at
+    T/Tc = tr and a given kappa~: at fixed kappa~ a smaller a gives a thicker
+    interface.  The coexistence densities do not depend on a."""
+    rv, rl = W.COEX_B_TABLE[tr]
+    return W.Workload(name=f"drop-a{a}-{tr}-{nu}", lattice=0, n=(N, N), bc=(0, 0), precision=0, eos=_eos(a),
+                      T_over_Tc=tr, kappa_tilde=kappa, nu_liquid=nu, nu_vapour=nu, rho_v=rv, rho_l=rl,
+                      kind="drop", radius=R, width=width, centre=((N - 1) / 2, (N - 1) / 2))
+
+
+def spurious_vs_a(avals, tr: float = W.TR_OF_RATIO[1000], nu: float = 0.1,
+                  collisions=(E.ELMRT_BGK, E.ELMRT_ENTROPIC), steps: int = 4000, **kw):
+    """Maximum spurious current of resting drops at T/Tc = tr for several
+    attraction parameters a at the fixed kappa~ of a = 0.003 (Sec. 3.1.2:
+    the interface thickens as a decreases, and the currents fall)."""
+    kappa = W.kappa_w5(tr)
+    runs = [Run(drop_a(tr, a, nu, kappa, **kw), c) for c in collisions for a in avals]
+    rate = _run_batch(runs, steps)
+    return runs, rate
 
 
 # --------------------------------------------------- crown radius (Sec. 3.2, 3.3)

@@ -169,3 +169,32 @@ def test_stability_domain_bgk_vs_entropic():
         assert not table[(E.ELMRT_BGK, 0.005, u0)]
         assert table[(E.ELMRT_ENTROPIC, 0.005, u0)]
         assert table[(E.ELMRT_BGK, 0.04, u0)] and table[(E.ELMRT_ENTROPIC, 0.04, u0)]
+
+
+def test_surface_tension_exponent_below_08_and_corresponding_states():
+    """Laplace-law surface tension over T/Tc = 0.6 .. 0.8 with kappa~ held at
+    its T/Tc = 0.7 value, for a = 0.003, 0.0017 and 0.0011 (b = 0.095): the
+    fitted exponent of (1 - T/Tc) is 11/9 within 0.12 for every a, and the
+    three exponents agree within 0.05 (Sec. 3.1.2: Guggenheim's 11/9 away
+    from Tc, independent of the interaction parameters)."""
+    temps = [0.6, 0.65, 0.7, 0.75, 0.8]
+    m = S.surface_tension_map(temps, [0.003, 0.0017, 0.0011], R=40.0, kappa_at=0.7)
+    exps = []
+    for a, recs in m.items():
+        sig = [r["sigma"] for r in recs]
+        e, _ = S.fit_power(temps, sig)
+        say(f"a={a}: sigma {np.round(sig, 5).tolist()} exponent {e:.3f}")
+        exps.append(e)
+    assert all(abs(e - 11 / 9) < 0.12 for e in exps)
+    assert max(exps) - min(exps) < 0.05
+
+
+def test_spurious_currents_fall_with_thicker_interfaces():
+    """Resting drops at T/Tc = 0.5925 (ratio 1000), nu = 0.1, with kappa~
+    fixed: lowering a from 0.003 to 0.0011 thickens the interface and lowers
+    the maximum spurious current of the entropic collision (Sec. 3.1.2)."""
+    runs, _ = S.spurious_vs_a([0.003, 0.0017, 0.0011], collisions=(E.ELMRT_ENTROPIC,), steps=4000)
+    u = [r.umax for r in runs]
+    say(f"entropic spurious currents for a = 0.003, 0.0017, 0.0011: {[f'{x:.3e}' for x in u]}")
+    assert all(r.stable for r in runs)
+    assert u[0] > u[1] > u[2]
