@@ -52,6 +52,24 @@ __host__ __device__ constexpr int cy_(int i) { return (i / 3) % 3 - 1; }
 template <int D>
 __host__ __device__ constexpr int cz_(int i) { return D == 3 ? i / 9 - 1 : 0; }
 
+// Number of nonzero components of c_i.
+template <int D>
+__host__ __device__ constexpr int pair_class(int i)
+{
+    return (cx_<D>(i) != 0) + (cy_<D>(i) != 0) + (cz_<D>(i) != 0);
+}
+// The n-th direction of the upper half i > (Q-1)/2 (one per pair (c, -c)),
+// ordered by pair_class, then by index.
+template <int D>
+__host__ __device__ constexpr int stencil_pair(int n)
+{
+    constexpr int Q = (D == 2) ? 9 : 27;
+    for (int k = 1; k <= D; ++k)
+        for (int i = (Q + 1) / 2; i < Q; ++i)
+            if (pair_class<D>(i) == k && n-- == 0) return i;
+    return -1;
+}
+
 // Unsigned 32-bit division by a run-time constant (Granlund-Montgomery).
 struct FastDiv {
     uint32_t d, m, l;
@@ -436,15 +454,25 @@ __device__ __forceinline__ bool collide(T (&f)[Lat<D>::Q], A rho, const A (&j)[3
     for (int x = 0; x < 3; ++x)
 #pragma unroll
         for (int y = 0; y < 3; ++y) wxy[x][y] = irt * ig[0][x] * ig[1][y];
+    // layer by layer in z: the x-y weights inside a layer, the layer's z
+    // weight once on its sums
     T S = T(0), H = T(0);
 #pragma unroll
-    for (int i = 0; i < Q; ++i) {
-        const int x = cx_<D>(i) + 1, y = cy_<D>(i) + 1, z = cz_<D>(i) + 1;
-        const T h = f[i] - s[i];
-        const T hw = h * (wxy[x][y] * ig[2][z]);
-        S += s[i] * hw;
-        H += h * hw;
-        f[i] = h;
+    for (int z = ZL; z <= ZH; ++z) {
+        T Sl = T(0), Hl = T(0);
+#pragma unroll
+        for (int y = 0; y < 3; ++y)
+#pragma unroll
+            for (int x = 0; x < 3; ++x) {
+                const int i = x + 3 * y + 9 * (D == 3 ? z : 0);
+                const T h = f[i] - s[i];
+                const T hw = h * wxy[x][y];
+                Sl += s[i] * hw;
+                Hl += h * hw;
+                f[i] = h;
+            }
+        S += Sl * ig[2][z];
+        H += Hl * ig[2][z];
     }
     const bool entropic_gamma = pos && (A)H > Eps2<A>::v * rho;
     const T ch = entropic_gamma ? (T)(omega - A(1)) * S * rcp<T>(H) : T(0);
@@ -785,16 +813,22 @@ __device__ __forceinline__ void collide_tile(int b, const T* __restrict__ cur, T
             hoff[k] = (gx + g.n[0] * gy) * (int)sizeof(T);
         }
     }
+    // Entries k < NFULL lie inside the halo for every lane; the test of the
+    // others is formed where it is used, not held as a lane mask.
+    constexpr int NFULL = (HX * HY) / NT;
+    auto staged = [&](int k) { return (int)opaque_v((uint32_t)hoff[k]) >= 0; };
     auto fetch_plane = [&](int m, T (&r)[NE]) {
         int dummy = 0;
-        const char* rp = plane_ptr(rho + (size_t)map_coord(m, g.n[MA], g.wall[MA], &dummy) * mstride);
+        const auto Rr = block_rsrc(rho + (size_t)map_coord(m, g.n[MA], g.wall[MA], &dummy) * mstride,
+                                   (uint32_t)mstride * (uint32_t)sizeof(T));
 #pragma unroll
-        for (int k = 0; k < NE; ++k) r[k] = (hoff[k] >= 0) ? pld<T>(rp, (uint32_t)hoff[k]) : T(0);
+        for (int k = 0; k < NE; ++k)
+            r[k] = (k < NFULL || staged(k)) ? bld<T>(Rr, (uint32_t)hoff[k], 0u) : T(0);
     };
     auto stage_plane = [&](int slot, const T (&r)[NE]) {
 #pragma unroll
         for (int k = 0; k < NE; ++k) {
-            if (hoff[k] >= 0) {
+            if (k < NFULL || staged(k)) {
                 const int e = lid + k * NT;
                 (&tpsi[slot][0][0])[e] = psi_signed<double>((double)r[k], ph);
                 (&trho[slot][0][0])[e] = r[k];
@@ -830,16 +864,18 @@ __device__ __forceinline__ void collide_tile(int b, const T* __restrict__ cur, T
             else pull_m<D, T, false>(cur, L, P, f);
 #pragma unroll
             for (int a = 0; a < D; ++a) {
+                // q_a planes as buffer resources: in-plane byte offsets, no
+                // 64-bit address arithmetic per load
                 const T* qa = q + (size_t)a * g.N;
-                const char* qm0 = plane_ptr(qa + (size_t)P.m * P.stride);
+                const auto Rm = block_rsrc(qa + (size_t)P.m * P.stride, P.bytes);
                 if (a == MA) {
-                    qn[a][0] = pld<T>(plane_ptr(qa + (size_t)P.mo[0] * P.stride), L.ip);
-                    qn[a][2] = pld<T>(plane_ptr(qa + (size_t)P.mo[2] * P.stride), L.ip);
-                    qn[a][1] = (P.mok[0] && P.mok[2]) ? T(0) : pld<T>(qm0, L.ip);
+                    qn[a][0] = bld<T>(block_rsrc(qa + (size_t)P.mo[0] * P.stride, P.bytes), L.ip, 0u);
+                    qn[a][2] = bld<T>(block_rsrc(qa + (size_t)P.mo[2] * P.stride, P.bytes), L.ip, 0u);
+                    qn[a][1] = (P.mok[0] && P.mok[2]) ? T(0) : bld<T>(Rm, L.ip, 0u);
                 } else {
-                    qn[a][0] = (a == 0) ? pld<T>(qm0, L.xo[0] + L.yo[1]) : pld<T>(qm0, L.xo[1] + L.yo[0]);
-                    qn[a][2] = (a == 0) ? pld<T>(qm0, L.xo[2] + L.yo[1]) : pld<T>(qm0, L.xo[1] + L.yo[2]);
-                    qn[a][1] = clear ? T(0) : pld<T>(qm0, L.ip);
+                    qn[a][0] = (a == 0) ? bld<T>(Rm, L.xo[0] + L.yo[1], 0u) : bld<T>(Rm, L.xo[1] + L.yo[0], 0u);
+                    qn[a][2] = (a == 0) ? bld<T>(Rm, L.xo[2] + L.yo[1], 0u) : bld<T>(Rm, L.xo[1] + L.yo[2], 0u);
+                    qn[a][1] = clear ? T(0) : bld<T>(Rm, L.ip, 0u);
                 }
             }
         }
@@ -876,35 +912,46 @@ __device__ __forceinline__ void collide_tile(int b, const T* __restrict__ cur, T
             // [4/3 psi(r+c_i) - 1/6 psi(r+2c_i)] and [rho(r+2c_i) - 2 rho(r+c_i)],
             // taken over the pairs (c, -c) so that each pair costs one
             // difference per radius; 3 w_i = 3 (1/6)^k (2/3)^(D-k) for k
-            // nonzero components.  FP64 throughout: at an interface the terms
-            // are O(1) and the force is divided by the vapour density.
+            // nonzero components.  The pairs run class by class (k = 1, 2, 3):
+            // the weight falls by exactly 4 from one class to the next, so the
+            // sums carry the unnormalised terms 8 d1 - d2 and d2 - 2 d1, are
+            // scaled by 4 between classes, and take the last class's weight at
+            // the end.  psi and its differences are FP64 (at an interface the
+            // terms are O(1) and the force is divided by the vapour density);
+            // the density differences are formed in the storage precision,
+            // whose rounding (relative to the difference) is below that of the
+            // stored densities themselves, and summed in FP64.
             double G[3] = {0.0, 0.0, 0.0}, K[3] = {0.0, 0.0, 0.0};
+            auto psi_at = [&](int d, int oy, int ox) { return fabs(tpsi[sl[d]][oy][ox]); };
+            auto rho_at = [&](int d, int oy, int ox) { return trho[sl[d]][oy][ox]; };
 #pragma unroll
-            for (int i = (Q + 1) / 2; i < Q; ++i) {
+            for (int n = 0; n < (Q - 1) / 2; ++n) {
+                const int i = stencil_pair<D>(n);
                 const int cx = cx_<D>(i), cy = cy_<D>(i), cz = cz_<D>(i);
-                const int k = (cx != 0) + (cy != 0) + (cz != 0);
-                const double w = (k == 1) ? ((D == 3) ? 2.0 / 9.0 : 1.0 / 3.0)
-                                          : (k == 2) ? ((D == 3) ? 1.0 / 18.0 : 1.0 / 12.0) : 1.0 / 72.0;
-                V2<double> p1, p2, m1, m2;
-                auto at = [&](int d, int oy, int ox) {
-                    V2<double> v;
-                    v.psi = tpsi[sl[d]][oy][ox];
-                    v.rho = (double)trho[sl[d]][oy][ox];
-                    return v;
-                };
-                if (D == 3) {
-                    p1 = at(2 + cz, hy0 + cy, tx + 2 + cx);
-                    p2 = at(2 + 2 * cz, hy0 + 2 * cy, tx + 2 + 2 * cx);
-                    m1 = at(2 - cz, hy0 - cy, tx + 2 - cx);
-                    m2 = at(2 - 2 * cz, hy0 - 2 * cy, tx + 2 - 2 * cx);
-                } else {
-                    p1 = at(2 + cy, 0, tx + 2 + cx);
-                    p2 = at(2 + 2 * cy, 0, tx + 2 + 2 * cx);
-                    m1 = at(2 - cy, 0, tx + 2 - cx);
-                    m2 = at(2 - 2 * cy, 0, tx + 2 - 2 * cx);
+                if (n > 0 && pair_class<D>(i) != pair_class<D>(stencil_pair<D>(n - 1))) {
+#pragma unroll
+                    for (int a = 0; a < D; ++a) {
+                        G[a] *= 4.0;
+                        K[a] *= 4.0;
+                    }
                 }
-                const double tt = (w * (4.0 / 3.0)) * (fabs(p1.psi) - fabs(m1.psi)) - (w * (1.0 / 6.0)) * (fabs(p2.psi) - fabs(m2.psi));
-                const double kk = w * (p2.rho - m2.rho) - (2.0 * w) * (p1.rho - m1.rho);
+                double d1p, d2p;
+                T d1r, d2r;
+                if (D == 3) {
+                    d1p = psi_at(2 + cz, hy0 + cy, tx + 2 + cx) - psi_at(2 - cz, hy0 - cy, tx + 2 - cx);
+                    d2p = psi_at(2 + 2 * cz, hy0 + 2 * cy, tx + 2 + 2 * cx) -
+                          psi_at(2 - 2 * cz, hy0 - 2 * cy, tx + 2 - 2 * cx);
+                    d1r = rho_at(2 + cz, hy0 + cy, tx + 2 + cx) - rho_at(2 - cz, hy0 - cy, tx + 2 - cx);
+                    d2r = rho_at(2 + 2 * cz, hy0 + 2 * cy, tx + 2 + 2 * cx) -
+                          rho_at(2 - 2 * cz, hy0 - 2 * cy, tx + 2 - 2 * cx);
+                } else {
+                    d1p = psi_at(2 + cy, 0, tx + 2 + cx) - psi_at(2 - cy, 0, tx + 2 - cx);
+                    d2p = psi_at(2 + 2 * cy, 0, tx + 2 + 2 * cx) - psi_at(2 - 2 * cy, 0, tx + 2 - 2 * cx);
+                    d1r = rho_at(2 + cy, 0, tx + 2 + cx) - rho_at(2 - cy, 0, tx + 2 - cx);
+                    d2r = rho_at(2 + 2 * cy, 0, tx + 2 + 2 * cx) - rho_at(2 - 2 * cy, 0, tx + 2 - 2 * cx);
+                }
+                const double tt = fma(8.0, d1p, -d2p);
+                const double kk = fma(-2.0, (double)d1r, (double)d2r);
                 const int c[3] = {cx, cy, cz};
 #pragma unroll
                 for (int a = 0; a < 3; ++a) {
@@ -914,7 +961,7 @@ __device__ __forceinline__ void collide_tile(int b, const T* __restrict__ cur, T
                 // a few pairs at a time, so that only their LDS values are live:
                 // the sums so far are pinned here and later LDS loads may not
                 // move above this point
-                if ((i - (Q + 1) / 2) % 4 == 3)
+                if (n % 4 == 3)
                     asm volatile("" : "+v"(G[0]), "+v"(G[1]), "+v"(G[2]), "+v"(K[0]), "+v"(K[1]), "+v"(K[2])::"memory");
             }
             double rhoc, j[3];
@@ -926,9 +973,13 @@ __device__ __forceinline__ void collide_tile(int b, const T* __restrict__ cur, T
             const double omega = omega_of<double>(rhoc, ph);
             double F[3] = {0.0, 0.0, 0.0}, Phi[3] = {0.0, 0.0, 0.0};
             const double half_rate = (1.0 - 0.5 * omega) * 0.5;
+            // the last class's weight 3 w = 1/72 (D3Q27, k = 3) or 1/12 (D2Q9,
+            // k = 2); the psi sum also takes the 1/6 of its unnormalised terms
+            constexpr double wl = (D == 3) ? 1.0 / 72.0 : 1.0 / 12.0;
+            const double cg = c0psi * (wl / 3.0), ck = ph.kappa * wl * rhoc;
 #pragma unroll
             for (int a = 0; a < D; ++a) {
-                F[a] = 2.0 * c0psi * G[a] + ph.kappa * rhoc * K[a];
+                F[a] = cg * G[a] + ck * K[a];
                 Phi[a] = half_rate * dq[a];
             }
             const bool fell_back = collide<D, T, double>(f, rhoc, j, F, Phi, omega, ph.entropic);
