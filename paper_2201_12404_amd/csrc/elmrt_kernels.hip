@@ -851,8 +851,13 @@ __device__ __forceinline__ void collide_tile(int b, const T* __restrict__ cur, T
     // Per plane: the density loads of the plane entering the window go out
     // first (staging waits only for them), then the Q population pulls and the
     // flux loads for Phi; psi is computed and staged while those are in flight.
+    // LDS slot of plane m - 2 is (m - m0) mod 5: a rotation counter kept
+    // uniform (scalar), so that the slot arithmetic is not done per lane
+    int rot = 0;
 #pragma unroll 1
     for (int m = t.m0; m < t.m1; ++m) {
+        const int r0 = __builtin_amdgcn_readfirstlane(rot);
+        rot = (r0 == 4) ? 0 : r0 + 1;
         PlanePull P;
         plane_setup<D, T>(g, m, P);
         T f[Q];
@@ -879,7 +884,7 @@ __device__ __forceinline__ void collide_tile(int b, const T* __restrict__ cur, T
                 }
             }
         }
-        stage_plane((m - t.m0 + 4) % 5, rn);
+        stage_plane(r0 == 0 ? 4 : r0 - 1, rn);
         __syncthreads();
         if (active) {
             // flux differences for Phi, formed as soon as the loads are back so
@@ -905,7 +910,7 @@ __device__ __forceinline__ void collide_tile(int b, const T* __restrict__ cur, T
 
             int sl[5];
 #pragma unroll
-            for (int d = 0; d < 5; ++d) sl[d] = (m - t.m0 + d) % 5;   // plane m + d - 2
+            for (int d = 0; d < 5; ++d) sl[d] = (r0 + d >= 5) ? r0 + d - 5 : r0 + d;   // plane m + d - 2
             const int hy0 = (D == 3) ? ty + 2 : 0;
             const double c0psi = tpsi[sl[2]][hy0][tx + 2];
             // force stencils (Sec. 2.3): sums of 3 w_i c_i times
@@ -951,7 +956,7 @@ __device__ __forceinline__ void collide_tile(int b, const T* __restrict__ cur, T
                     d2r = rho_at(2 + 2 * cy, 0, tx + 2 + 2 * cx) - rho_at(2 - 2 * cy, 0, tx + 2 - 2 * cx);
                 }
                 const double tt = fma(8.0, d1p, -d2p);
-                const double kk = fma(-2.0, (double)d1r, (double)d2r);
+                const double kk = (double)fma(T(-2), d1r, d2r);   // one rounding, relative to kk
                 const int c[3] = {cx, cy, cz};
 #pragma unroll
                 for (int a = 0; a < 3; ++a) {
