@@ -358,6 +358,9 @@ def main():
             "unit": "GB/s",
             "frac": round(achieved / HBM_PEAK_GBS, 4),
             "traffic": traffic,
+            # counted HBM bytes per launch over the live launch time: the
+            # rate at the memory interface, re-reads included
+            "traffic_gbs": round(traffic / avg_collide_s / 1e9, 1) if traffic else None,
             "bytes_per_cell": b_collide,
         },
         "diagnostics": {"mass_drift": sums[0] / mass0 - 1.0, "gamma_fallbacks": fallbacks,
