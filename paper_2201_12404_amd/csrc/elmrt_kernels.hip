@@ -566,18 +566,19 @@ __device__ __forceinline__ double bld<double>(__amdgpu_buffer_rsrc_t r, uint32_t
 {
     return __builtin_bit_cast(double, __builtin_amdgcn_raw_buffer_load_b64(r, (int)voff, (int)soff, 0));
 }
-template <typename T>
-__device__ __forceinline__ void bst(__amdgpu_buffer_rsrc_t r, uint32_t voff, uint32_t soff, T v);
-template <>
-__device__ __forceinline__ void bst<float>(__amdgpu_buffer_rsrc_t r, uint32_t voff, uint32_t soff, float v)
+// Buffer stores; POLICY is the cache-policy operand (0: default; kStream:
+// the nt bit, for data that is not read again before far more data than the
+// caches hold has passed).
+constexpr int kStream = 2;
+template <typename T, int POLICY = 0>
+__device__ __forceinline__ void bst(__amdgpu_buffer_rsrc_t r, uint32_t voff, uint32_t soff, T v)
 {
-    __builtin_amdgcn_raw_buffer_store_b32(__builtin_bit_cast(uint32_t, v), r, (int)voff, (int)soff, 0);
-}
-template <>
-__device__ __forceinline__ void bst<double>(__amdgpu_buffer_rsrc_t r, uint32_t voff, uint32_t soff, double v)
-{
-    using u2 = __attribute__((ext_vector_type(2))) uint32_t;
-    __builtin_amdgcn_raw_buffer_store_b64(__builtin_bit_cast(u2, v), r, (int)voff, (int)soff, 0);
+    if constexpr (sizeof(T) == 4) {
+        __builtin_amdgcn_raw_buffer_store_b32(__builtin_bit_cast(uint32_t, v), r, (int)voff, (int)soff, POLICY);
+    } else {
+        using u2 = __attribute__((ext_vector_type(2))) uint32_t;
+        __builtin_amdgcn_raw_buffer_store_b64(__builtin_bit_cast(u2, v), r, (int)voff, (int)soff, POLICY);
+    }
 }
 
 // In-plane pull sources of one lane, source coordinate x - c (c = -1, 0, +1),
@@ -997,7 +998,11 @@ __device__ __forceinline__ void collide_tile(int b, const T* __restrict__ cur, T
                 const uint32_t pb = opaque(P.bytes);
                 const auto R = block_of<D, T>(nxt, P, P.m);
 #pragma unroll
-                for (int i = 0; i < Q; ++i) bst<T>(R, L.ip, (uint32_t)i * pb, f[i]);
+                // the new populations are read again only by the next step,
+                // after the whole population array has streamed through: the
+                // stores bypass cache retention (2 % off the step on 256^3,
+                // mostly in the next moment pass)
+                for (int i = 0; i < Q; ++i) bst<T, kStream>(R, L.ip, (uint32_t)i * pb, f[i]);
             }
         }
         __syncthreads();
