@@ -101,10 +101,17 @@ def _run_batch(runs, steps: int, checkpoints=()):
 
 
 def spurious_currents(temps, nus, collisions=(E.ELMRT_BGK, E.ELMRT_ENTROPIC), steps: int = 4000, N: int = 128,
-                      R: float = 25.0, checkpoints=(), precision: int = 0):
+                      R: float = 25.0, checkpoints=(), precision: int = 0, kappa_at: float | None = None):
     """Max spurious current after 'steps' for every (T/Tc, nu, collision);
-    returns (runs, lattice updates per second of the batched run)."""
-    runs = [Run(drop(tr, nu, N, R, precision=precision), c) for c in collisions for tr in temps for nu in nus]
+    returns (runs, lattice updates per second of the batched run).  kappa~
+    follows T (interface width ~5 at every T) unless kappa_at names the
+    T/Tc whose kappa~ all cases share."""
+    def case(tr, nu):
+        if kappa_at is None:
+            return drop(tr, nu, N, R, precision=precision)
+        w = drop_a(tr, 0.003, nu, W.kappa_w5(kappa_at), N=N, R=R)
+        return replace(w, precision=precision)
+    runs = [Run(case(tr, nu), c) for c in collisions for tr in temps for nu in nus]
     rate = _run_batch(runs, steps, checkpoints)
     return runs, rate
 

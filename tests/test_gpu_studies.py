@@ -86,6 +86,20 @@ def test_spurious_current_temperature_exponent():
     assert all(np.isfinite(u)) and 1.0 < m < 4.0
 
 
+def test_spurious_current_temperature_exponent_fixed_kappa():
+    """The same fit with kappa~ held at its T/Tc = 0.7 value and nu = 0.03
+    (entropic, 4000 steps): m within 0.4 of the paper's 2.2 (Sec. 3.1.2), and
+    the currents fall monotonically towards Tc."""
+    temps = [0.6, 0.65, 0.7, 0.75, 0.8]
+    runs, _ = S.spurious_currents(temps, [0.03], collisions=(E.ELMRT_ENTROPIC,), steps=4000, kappa_at=0.7)
+    u = [r.umax for r in runs]
+    m, c = S.fit_power(temps, u)
+    say(f"spurious currents at fixed kappa {dict(zip(temps, u))}; fit m = {m:.2f}, C = {c:.3e}")
+    assert all(r.stable for r in runs)
+    assert all(a > b for a, b in zip(u, u[1:]))
+    assert abs(m - 2.2) < 0.4
+
+
 def test_coexistence_matches_maxwell():
     """Flat interfaces (800 x 10, liquid column 400 wide, a = 0.003,
     b = 0.095, FP32) converged to 1e-9 in the max norm: the liquid density
