@@ -98,3 +98,19 @@ def test_impact_we_re_dimensionless_groups():
         assert w.centre[-1] - w.radius - w.film == pytest.approx(2 * w.width)
     assert S.impact_we_re(93, 100, R0, sigma).n == (1200, 600)
     assert S.impact_we_re(93, 100, R0, sigma, D=3).n == (700, 700, 300)
+
+
+def test_fixed_kappa_drops_differ_from_the_default_only_in_kappa():
+    """The fixed-kappa~ resting drops of the temperature study use the same
+    EOS, coexistence densities and geometry as the default ones; only kappa~
+    is the one of T/Tc = 0.7 for every T."""
+    k07 = W.kappa_w5(0.7)
+    for tr in (0.6, 0.65, 0.7, 0.75, 0.8):
+        ref = S.drop(tr, 0.03)
+        w = S.drop_a(tr, 0.003, 0.03, k07)
+        assert w.eos == W.EOS_B
+        assert (w.rho_v, w.rho_l) == (ref.rho_v, ref.rho_l)
+        assert (w.n, w.radius, w.width, w.centre, w.nu_liquid, w.nu_vapour) == \
+            (ref.n, ref.radius, ref.width, ref.centre, ref.nu_liquid, ref.nu_vapour)
+        assert w.kappa_tilde == k07
+        assert (ref.kappa_tilde == k07) == (tr == 0.7)
