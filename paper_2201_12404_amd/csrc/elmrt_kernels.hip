@@ -327,12 +327,11 @@ __device__ __forceinline__ bool collide(T (&f)[Lat<D>::Q], A rho, const A (&j)[3
     const A inv_rho = rcp<A>(rho);
     A u[3] = {A(0), A(0), A(0)};
     A e[3][3], gs[3][3];
-    bool pos = rho > A(0);
 #pragma unroll
     for (int a = 0; a < 3; ++a) {
         if (a >= D) {
-            e[a][0] = e[a][2] = gs[a][0] = gs[a][2] = A(0);
-            e[a][1] = gs[a][1] = A(1);
+            e[a][0] = e[a][2] = A(0);
+            e[a][1] = A(1);
             continue;
         }
         u[a] = j[a] * inv_rho;
@@ -340,15 +339,10 @@ __device__ __forceinline__ bool collide(T (&f)[Lat<D>::Q], A rho, const A (&j)[3
         e[a][1] = A(1) - zeta;
         e[a][2] = A(0.5) * (zeta + u[a]);
         e[a][0] = A(0.5) * (zeta - u[a]);
-        const A xs = u[a] + F[a] * inv_rho;
-        const A zs = third + xs * xs + Phi[a] * inv_rho;
-        gs[a][1] = A(1) - zs;
-        gs[a][2] = A(0.5) * (zs + xs);
-        gs[a][0] = A(0.5) * (zs - xs);
-        pos = pos && gs[a][0] > A(0) && gs[a][1] > A(0) && gs[a][2] > A(0);
     }
     // pass 1: f - f^eq (f^eq formed in A from rho times its x-y factor
-    // product and the z factor; the difference is small)
+    // product and the z factor; the difference is small).  It follows the
+    // moments directly, so that their widened copies of f serve it as well.
 #pragma unroll
     for (int x = 0; x < 3; ++x)
 #pragma unroll
@@ -360,6 +354,21 @@ __device__ __forceinline__ bool collide(T (&f)[Lat<D>::Q], A rho, const A (&j)[3
                 f[i] = (T)((A)f[i] - re * e[2][z]);
             }
         }
+    bool pos = rho > A(0);
+#pragma unroll
+    for (int a = 0; a < 3; ++a) {
+        if (a >= D) {
+            gs[a][0] = gs[a][2] = A(0);
+            gs[a][1] = A(1);
+            continue;
+        }
+        const A xs = u[a] + F[a] * inv_rho;
+        const A zs = third + xs * xs + Phi[a] * inv_rho;
+        gs[a][1] = A(1) - zs;
+        gs[a][2] = A(0.5) * (zs + xs);
+        gs[a][0] = A(0.5) * (zs - xs);
+        pos = pos && gs[a][0] > A(0) && gs[a][1] > A(0) && gs[a][2] > A(0);
+    }
     // second moments of f - f^eq (its mass and momentum vanish, so raw and
     // central moments agree), from sums and differences along x lines
     T Pxx = T(0), Pyy = T(0), Pzz = T(0), Pxy = T(0), Pxz = T(0), Pyz = T(0);
@@ -972,10 +981,6 @@ __device__ __forceinline__ void collide_tile(int b, const T* __restrict__ cur, T
             }
             double rhoc, j[3];
             moments<D, T, double>(f, rhoc, j);
-            // the FP64 copies of f made for the moments are not kept for the
-            // collision (it converts again): 2Q fewer registers at its peak
-#pragma unroll
-            for (int i = 0; i < Q; ++i) asm volatile("" : "+v"(f[i]));
             const double omega = omega_of<double>(rhoc, ph);
             double F[3] = {0.0, 0.0, 0.0}, Phi[3] = {0.0, 0.0, 0.0};
             const double half_rate = (1.0 - 0.5 * omega) * 0.5;
