@@ -726,7 +726,8 @@ struct TileCoords {
     int x0, y0, m0, m1;
 };
 
-template <int D, int TX, int TY>
+// TOP_DOWN: plane blocks in descending order of the workgroup index.
+template <int D, int TX, int TY, bool TOP_DOWN = false>
 __device__ __forceinline__ TileCoords tile_of(const Grid& g, int b, int bx, int by, int tm)
 {
     TileCoords t;
@@ -737,6 +738,7 @@ __device__ __forceinline__ TileCoords tile_of(const Grid& g, int b, int bx, int 
         yb = b % by;
         b /= by;
     }
+    if (TOP_DOWN) b = (g.n[D - 1] + tm - 1) / tm - 1 - b;
     t.x0 = xb * TX;
     t.y0 = yb * TY;
     t.m0 = b * tm;
@@ -751,7 +753,10 @@ __device__ __forceinline__ void macro_tile(int b, const T* __restrict__ cur, T* 
                                            int bx, int by, int tm)
 {
     constexpr int Q = Lat<D>::Q;
-    const TileCoords t = tile_of<D, TX, TY>(g, b, bx, by, tm);
+    // top-down: the planes read last are the bottom ones, which the collision
+    // pass (bottom-up) reads first, partly from the Infinity Cache (0.6 % off
+    // the step on 256^3)
+    const TileCoords t = tile_of<D, TX, TY, true>(g, b, bx, by, tm);
     const int x = t.x0 + (int)threadIdx.x;
     const int y = (D == 3) ? t.y0 + (int)threadIdx.y : 0;
     if (x >= g.n[0] || (D == 3 && y >= g.n[1])) return;
