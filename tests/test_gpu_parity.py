@@ -481,3 +481,38 @@ def test_checkpoint_resume_bitwise(D, prec):
         other.load_state(snap)
     for s in (a, b, other):
         s.close()
+
+
+@pytest.mark.parametrize("D", [2, 3])
+def test_fp64_pressure_above_p0_branch(D):
+    """The minus branch of the psi term (P > P0, reading R3) against the
+    oracle, FP64, element by element after 25 steps.  A Peng-Robinson gas
+    (a = 1.5, b = 0.5, T/Tc = 0.99) at rho = 0.15 +- 0.03 has P > P0 in most
+    cells and P < P0 in the rest, so both branches and the crossing are
+    exercised (counted by the oracle)."""
+    n = (70, 44, 1) if D == 2 else (70, 13, 30)
+    bc = (0, 1, 0) if D == 2 else (0, 0, 1)
+    p = E.Params(lattice=D - 2, n=n, precision=E.ELMRT_FP64, bc=bc, eos_a=1.5, eos_b=0.5, T_over_Tc=0.99,
+                 kappa_tilde=0.05, nu_liquid=0.05, nu_vapour=0.05)
+    N = p.N
+    x = np.arange(N) % n[0]
+    y = (np.arange(N) // n[0]) % n[1]
+    rho0 = 0.15 + 0.03 * np.sin(2 * np.pi * x / n[0]) * np.cos(2 * np.pi * (y + 0.5) / n[1])
+    u0 = np.random.default_rng(21).uniform(-1e-3, 1e-3, (D, N))
+    say(f"[gpu] P > P0 branch D={D} n={n}")
+    sim = E.Simulation(p)
+    sim.init_fields(rho0, u0)
+    sim.step(25)
+    rho_g, u_g, s_g = sim.read_macros()
+    f_g = sim.read_populations()
+    sim.close()
+    op = O.Params(D=D, n=n, bc=bc, a=1.5, b=0.5, Tr=0.99, kappa=0.05, nu_l=0.05, nu_v=0.05)
+    f = O.init_fluid(op, rho0, u0)
+    first = O.step(op, f, 1)
+    last = O.step(op, f, 24)
+    rho_o, u_o, s_o = O.macros(op, f)
+    say(f"P > P0 cells: step 1 {first.cells_p_above_p0} of {N}, step 25 {last.cells_p_above_p0}")
+    assert 0 < first.cells_p_above_p0 < N
+    assert rel_max(rho_g, rho_o) < 1e-12 and rel_max(u_g, u_o) < 1e-12
+    m = velocity_map(E.elmrt_velocities(p.lattice), D)
+    np.testing.assert_allclose(f_g.T, f[:, m], rtol=0, atol=1e-13 * np.abs(f).max())
