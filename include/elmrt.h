@@ -44,7 +44,7 @@ typedef enum {
     ELMRT_E_INVALID = 1,   /* bad argument or parameter; nothing was enqueued */
     ELMRT_E_NOMEM = 2,     /* workspace too small or host allocation failed */
     ELMRT_E_DEVICE = 3,    /* a HIP call failed; the handle may be unusable */
-    ELMRT_E_UNSTABLE = 4,  /* a non-finite or non-positive density was seen (sticky) */
+    ELMRT_E_UNSTABLE = 4,  /* a non-finite, non-positive or >= 1/b density was seen (sticky) */
     ELMRT_E_STATE = 5      /* call out of order (e.g. step before init_fields) */
 } elmrt_status;
 
@@ -111,9 +111,13 @@ elmrt_status elmrt_step_timed(elmrt_sim* s, int64_t nsteps, double ms[2]);
 
 /* Read rho(t) and the bare velocity u = sum c f / rho (Sec. 2.2) of the
  * current state into host FP64 arrays (either may be NULL), and the sums
- * [sum rho, sum rho u_x, sum rho u_y, sum rho u_z] accumulated in FP64
- * (sums may be NULL).  Synchronises.  Returns ELMRT_E_UNSTABLE (outputs still
- * filled) once a non-finite or non-positive density has been seen. */
+ * [sum rho, sum rho u_x, sum rho u_y, sum rho u_z] (sums may be NULL),
+ * accumulated in FP64 with Neumaier's compensated summation per thread,
+ * across the lanes of each wavefront, the wavefronts of each workgroup and
+ * the 1024 workgroup partials in order.  Synchronises.  Returns
+ * ELMRT_E_UNSTABLE (outputs still filled) once a non-finite or non-positive
+ * density, or one at or beyond 1/b (the pole of the Peng-Robinson pressure,
+ * Sec. 3.1), has been seen by a step or a read-out. */
 elmrt_status elmrt_read_macros(elmrt_sim* s, double* rho, double* u, double* sums);
 
 /* Fluid velocity u + F dt/(2 rho) of the exact-difference forcing (Sec. 2.3,

@@ -197,7 +197,7 @@ Layout layout_of(const elmrt_params* p)
     L.rho = o;      o = align_up(o + N * es);
     L.q = o;        o = align_up(o + (size_t)D * N * es);
     L.flag = o;     o = align_up(o + 256);
-    L.partials = o; o = align_up(o + (size_t)kReadBlocks * 4 * sizeof(double));
+    L.partials = o; o = align_up(o + (size_t)kReadBlocks * 8 * sizeof(double));
     L.total = o;
     return L;
 }
@@ -387,7 +387,7 @@ static elmrt_status step_impl(elmrt_sim* s, int64_t nsteps, hipEvent_t* ev)
     for (int64_t k = 0; k < nsteps; ++k) {
         void* cur = s->buf[s->cur];
         void* nxt = s->buf[1 - s->cur];
-        e = elmrt::launch_macro(s->L, cur, s->rho, s->q, s->flag);
+        e = elmrt::launch_macro(s->L, cur, s->rho, s->q, s->flag, 1.0 / s->ph.b);
         if (e != hipSuccess) return hip_fail(e, "moment kernel");
         if (ev && (e = hipEventRecord(ev[2 * k + 1], s->stream)) != hipSuccess) return hip_fail(e, "hipEventRecord");
         e = elmrt::launch_collide(s->L, s->tx, s->ty, member_depth(s, cap), cur, nxt, s->rho, s->q, s->ph, s->flag);
@@ -433,13 +433,13 @@ static elmrt_status read_impl(elmrt_sim* s, double* rho, double* u, double* sums
     char* tmp = (char*)s->buf[1 - s->cur];
     void* trho = tmp;
     void* tu = tmp + s->N * s->es;
-    hipError_t e = elmrt::launch_readout(s->L, s->buf[s->cur], trho, tu, s->partials, kReadBlocks, s->flag);
+    hipError_t e = elmrt::launch_readout(s->L, s->buf[s->cur], trho, tu, s->partials, kReadBlocks, s->flag, 1.0 / s->ph.b);
     if (e != hipSuccess) return hip_fail(e, "readout kernel");
     if (fluid && (e = elmrt::launch_fluid_velocity(s->L, trho, tu, s->ph)) != hipSuccess)
         return hip_fail(e, "velocity shift kernel");
     // only the fields asked for cross PCIe (density first, then velocity)
     std::vector<char> h(((u ? 1 + (size_t)s->D : (rho ? 1 : 0))) * s->N * s->es);
-    std::vector<double> part((size_t)kReadBlocks * 4);
+    std::vector<double> part((size_t)kReadBlocks * 8);
     unsigned flag = 0;
     e = h.empty() ? hipSuccess : hipMemcpyAsync(h.data(), tmp, h.size(), hipMemcpyDeviceToHost, s->stream);
     if (e == hipSuccess) e = hipMemcpyAsync(part.data(), s->partials, part.size() * sizeof(double), hipMemcpyDeviceToHost, s->stream);
@@ -455,19 +455,21 @@ static elmrt_status read_impl(elmrt_sim* s, double* rho, double* u, double* sums
         else widen<double>(h.data() + s->N * s->es, u, (size_t)s->D * s->N);
     }
     if (sums) {
-        // Neumaier summation of the per-block FP64 partials, in block order
+        // the blocks' (sum, correction) pairs merged in block order by
+        // Neumaier's compensated summation, as within the blocks
         for (int k = 0; k < 4; ++k) {
             double acc = 0.0, comp = 0.0;
             for (int b = 0; b < kReadBlocks; ++b) {
-                const double x = part[(size_t)b * 4 + k];
+                const double x = part[(size_t)b * 8 + 2 * k];
                 const double t = acc + x;
                 comp += (std::fabs(acc) >= std::fabs(x)) ? (acc - t) + x : (x - t) + acc;
                 acc = t;
+                comp += part[(size_t)b * 8 + 2 * k + 1];
             }
             sums[k] = acc + comp;
         }
     }
-    if (flag) return fail(ELMRT_E_UNSTABLE, "non-finite or non-positive density encountered");
+    if (flag) return fail(ELMRT_E_UNSTABLE, "non-finite, non-positive or >= 1/b density encountered");
     return ELMRT_OK;
 }
 

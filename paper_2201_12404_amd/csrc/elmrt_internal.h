@@ -65,7 +65,9 @@ struct Launch {
     hipStream_t stream;
 };
 
-hipError_t launch_macro(const Launch& L, const void* cur, void* rho, void* q, unsigned* flag);
+// The instability flag is raised for a non-finite or non-positive density, or
+// one at or beyond rho_max = 1/b, the pole of the Peng-Robinson pressure.
+hipError_t launch_macro(const Launch& L, const void* cur, void* rho, void* q, unsigned* flag, double rho_max);
 
 hipError_t launch_collide(const Launch& L, int tx, int ty, int tm, const void* cur, void* nxt,
                           const void* rho, const void* q, const Phys<double>& ph, unsigned* flag);
@@ -80,10 +82,12 @@ hipError_t launch_fluid_velocity(const Launch& L, const void* rho, void* u, cons
 // f := f^eq(rho0, u0) stored so that pull-streaming yields f^eq at every cell.
 hipError_t launch_init(const Launch& L, const double* rho0, const double* u0, void* cur);
 
-// rho, u of the current state (working precision), per-block FP64 partial sums
-// of rho and rho u (nblocks x 4) and the instability flag.
+// rho, u of the current state (working precision; not written when rho is
+// NULL), per-block compensated FP64 sums of rho and rho u -- (sum,
+// correction) of quantity k of block b at partials[8 b + 2 k], nblocks x 8
+// doubles -- and the instability flag (as launch_macro).
 hipError_t launch_readout(const Launch& L, const void* cur, void* rho, void* u, double* partials,
-                          int nblocks, unsigned* flag);
+                          int nblocks, unsigned* flag, double rho_max);
 
 // f_i(r, t) = pulled populations, written to out[i*N + cell].
 hipError_t launch_pull(const Launch& L, const void* cur, void* out);

@@ -750,7 +750,7 @@ __device__ __forceinline__ TileCoords tile_of(const Grid& g, int b, int bx, int 
 template <int D, typename T, int TX, int TY>
 __device__ __forceinline__ void macro_tile(int b, const T* __restrict__ cur, T* __restrict__ rho_out,
                                            T* __restrict__ q_out, unsigned* __restrict__ flag, const Grid& g,
-                                           int bx, int by, int tm)
+                                           int bx, int by, int tm, double rho_max)
 {
     constexpr int Q = Lat<D>::Q;
     // top-down: the planes read last are the bottom ones, which the collision
@@ -784,7 +784,7 @@ __device__ __forceinline__ void macro_tile(int b, const T* __restrict__ cur, T* 
             const double ua = j[a] * inv;
             pst<T, true>(plane_ptr(q_out + (size_t)a * g.N + mself), L.ip, (T)(j[a] * ua * ua));
         }
-        bad = bad || !(rho > 0.0) || !isfinite(rho);
+        bad = bad || !(rho > 0.0) || !isfinite(rho) || rho >= rho_max;
     }
     if (bad) atomicOr(flag, 1u);
 }
@@ -1043,9 +1043,9 @@ __device__ __forceinline__ int row_xcd_order(int b, int nb, int bx)
 template <int D, typename T, int TX, int TY>
 __global__ __launch_bounds__(TX* TY) void k_macro(const T* __restrict__ cur, T* __restrict__ rho_out,
                                                   T* __restrict__ q_out, unsigned* __restrict__ flag, Grid g,
-                                                  int bx, int by, int tm)
+                                                  int bx, int by, int tm, double rho_max)
 {
-    macro_tile<D, T, TX, TY>((int)blockIdx.x, cur, rho_out, q_out, flag, g, bx, by, tm);
+    macro_tile<D, T, TX, TY>((int)blockIdx.x, cur, rho_out, q_out, flag, g, bx, by, tm, rho_max);
 }
 
 template <int D, typename T, int TX, int TY>
@@ -1079,7 +1079,7 @@ __global__ __launch_bounds__(TX* TY) void k_macro_batch(const BatchJob* __restri
     const int j = job_of(jobs, njobs, b, &BatchJob::mfirst);
     const BatchJob& J = jobs[j];
     macro_tile<D, T, TX, TY>(b - J.mfirst, (const T*)J.buf[J.cur0 ^ parity], (T*)J.rho, (T*)J.q, J.flag, J.g,
-                             J.mbx, J.mby, J.mtm);
+                             J.mbx, J.mby, J.mtm, 1.0 / J.ph.b);
 }
 
 template <int D, typename T, int TX, int TY>
@@ -1194,13 +1194,41 @@ __global__ __launch_bounds__(256) void k_init(const double* __restrict__ rho0, c
     }
 }
 
+// Neumaier's compensated sum: s plus a running correction c for the low-order
+// bits that each addition to s loses.  Pairs merge by adding the other sum to
+// s and the other correction to c.
+struct CSum {
+    double s, c;
+};
+
+__device__ __forceinline__ void csum_add(CSum& a, double x)
+{
+    const double t = a.s + x;
+    a.c += (fabs(a.s) >= fabs(x)) ? (a.s - t) + x : (x - t) + a.s;
+    a.s = t;
+}
+
+__device__ __forceinline__ void csum_merge(CSum& a, const CSum& b)
+{
+    csum_add(a, b.s);
+    a.c += b.c;
+}
+
+// rho and u of every cell (working precision; skipped when rho_out is NULL),
+// and per-block compensated sums of rho and rho u: each thread accumulates
+// its cells, the 64 lanes of a wavefront merge by shuffles, and the four
+// wavefronts of the block in order; block b writes (sum, correction) of
+// quantity k at partials[8 b + 2 k].  The instability flag is raised for a
+// non-finite or non-positive density, or one at or beyond 1/b (the pole of
+// the Peng-Robinson pressure).
 template <int D, typename T>
 __global__ __launch_bounds__(256) void k_readout(const T* __restrict__ cur, T* __restrict__ rho_out,
                                                  T* __restrict__ u_out, double* __restrict__ partials,
-                                                 unsigned* __restrict__ flag, Grid g, FlatGrid fg)
+                                                 unsigned* __restrict__ flag, Grid g, FlatGrid fg, double rho_max)
 {
-    __shared__ double red[4][256];
-    double acc[4] = {0.0, 0.0, 0.0, 0.0};
+    __shared__ double red[4][4][2];
+    CSum acc[4] = {{0.0, 0.0}, {0.0, 0.0}, {0.0, 0.0}, {0.0, 0.0}};
+    bool bad = false;
     for (uint32_t cell = blockIdx.x * 256u + threadIdx.x; cell < (uint32_t)g.N; cell += gridDim.x * 256u) {
         int x, y, z;
         flat_coords(cell, fg, x, y, z);
@@ -1210,20 +1238,39 @@ __global__ __launch_bounds__(256) void k_readout(const T* __restrict__ cur, T* _
         pull<D, T>(cur, g, P, f);
         double rho, j[3];
         moments<D, T, double>(f, rho, j);
-        rho_out[cell] = (T)rho;
-        for (int a = 0; a < D; ++a) u_out[(size_t)a * g.N + cell] = (T)(j[a] / rho);
-        acc[0] += rho;
-        for (int a = 0; a < D; ++a) acc[1 + a] += j[a];
-        if (!(rho > 0.0) || !isfinite(rho)) atomicOr(flag, 1u);
+        if (rho_out) {
+            rho_out[cell] = (T)rho;
+            for (int a = 0; a < D; ++a) u_out[(size_t)a * g.N + cell] = (T)(j[a] / rho);
+        }
+        csum_add(acc[0], rho);
+        for (int a = 0; a < D; ++a) csum_add(acc[1 + a], j[a]);
+        bad = bad || !(rho > 0.0) || !isfinite(rho) || rho >= rho_max;
     }
-    for (int k = 0; k < 4; ++k) red[k][threadIdx.x] = acc[k];
+    if (bad) atomicOr(flag, 1u);
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1) {
+#pragma unroll
+        for (int k = 0; k < 4; ++k) {
+            CSum o;
+            o.s = __shfl_down(acc[k].s, off, 64);
+            o.c = __shfl_down(acc[k].c, off, 64);
+            csum_merge(acc[k], o);
+        }
+    }
+    const int wave = threadIdx.x >> 6;
+    if ((threadIdx.x & 63) == 0)
+        for (int k = 0; k < 4; ++k) {
+            red[wave][k][0] = acc[k].s;
+            red[wave][k][1] = acc[k].c;
+        }
     __syncthreads();
-    for (int s = 128; s > 0; s >>= 1) {
-        if ((int)threadIdx.x < s)
-            for (int k = 0; k < 4; ++k) red[k][threadIdx.x] += red[k][threadIdx.x + s];
-        __syncthreads();
+    if (threadIdx.x < 4) {
+        const int k = threadIdx.x;
+        CSum t = {red[0][k][0], red[0][k][1]};
+        for (int w = 1; w < 4; ++w) csum_merge(t, CSum{red[w][k][0], red[w][k][1]});
+        partials[blockIdx.x * 8 + 2 * k] = t.s;
+        partials[blockIdx.x * 8 + 2 * k + 1] = t.c;
     }
-    if (threadIdx.x < 4) partials[blockIdx.x * 4 + threadIdx.x] = red[threadIdx.x][0];
 }
 
 template <int D, typename T>
@@ -1317,12 +1364,12 @@ hipError_t collide_batch_dispatch(int tx, int ty, const BatchJob* jobs, int njob
 }
 
 template <int D, typename T>
-hipError_t macro_t(const Launch& L, const void* cur, void* rho, void* q, unsigned* flag)
+hipError_t macro_t(const Launch& L, const void* cur, void* rho, void* q, unsigned* flag, double rho_max)
 {
     const Tiling t = macro_tiling(D, L.g);
     if (t.blocks <= 0 || t.blocks > 0x7fffffffLL) return hipErrorInvalidConfiguration;
     hipLaunchKernelGGL((k_macro<D, T, kMacroTX, 1>), dim3((unsigned)t.blocks), dim3(kMacroTX, 1), 0, L.stream,
-                       (const T*)cur, (T*)rho, (T*)q, flag, L.g, t.bx, t.by, t.tm);
+                       (const T*)cur, (T*)rho, (T*)q, flag, L.g, t.bx, t.by, t.tm, rho_max);
     return hipGetLastError();
 }
 
@@ -1372,12 +1419,12 @@ Tiling collide_tiling(int D, const Grid& g, int tx, int ty, int tm)
     return t;
 }
 
-hipError_t launch_macro(const Launch& L, const void* cur, void* rho, void* q, unsigned* flag)
+hipError_t launch_macro(const Launch& L, const void* cur, void* rho, void* q, unsigned* flag, double rho_max)
 {
-    if (L.D == 2 && !L.fp64) return macro_t<2, float>(L, cur, rho, q, flag);
-    if (L.D == 2) return macro_t<2, double>(L, cur, rho, q, flag);
-    if (!L.fp64) return macro_t<3, float>(L, cur, rho, q, flag);
-    return macro_t<3, double>(L, cur, rho, q, flag);
+    if (L.D == 2 && !L.fp64) return macro_t<2, float>(L, cur, rho, q, flag, rho_max);
+    if (L.D == 2) return macro_t<2, double>(L, cur, rho, q, flag, rho_max);
+    if (!L.fp64) return macro_t<3, float>(L, cur, rho, q, flag, rho_max);
+    return macro_t<3, double>(L, cur, rho, q, flag, rho_max);
 }
 
 hipError_t launch_collide(const Launch& L, int tx, int ty, int tm, const void* cur, void* nxt,
@@ -1450,18 +1497,18 @@ hipError_t launch_init(const Launch& L, const double* rho0, const double* u0, vo
 }
 
 hipError_t launch_readout(const Launch& L, const void* cur, void* rho, void* u, double* partials, int nblocks,
-                          unsigned* flag)
+                          unsigned* flag, double rho_max)
 {
     const FlatGrid fg = flat_of(L.g);
     const dim3 grid(nblocks), block(256);
     if (L.D == 2 && !L.fp64)
-        hipLaunchKernelGGL((k_readout<2, float>), grid, block, 0, L.stream, (const float*)cur, (float*)rho, (float*)u, partials, flag, L.g, fg);
+        hipLaunchKernelGGL((k_readout<2, float>), grid, block, 0, L.stream, (const float*)cur, (float*)rho, (float*)u, partials, flag, L.g, fg, rho_max);
     else if (L.D == 2)
-        hipLaunchKernelGGL((k_readout<2, double>), grid, block, 0, L.stream, (const double*)cur, (double*)rho, (double*)u, partials, flag, L.g, fg);
+        hipLaunchKernelGGL((k_readout<2, double>), grid, block, 0, L.stream, (const double*)cur, (double*)rho, (double*)u, partials, flag, L.g, fg, rho_max);
     else if (!L.fp64)
-        hipLaunchKernelGGL((k_readout<3, float>), grid, block, 0, L.stream, (const float*)cur, (float*)rho, (float*)u, partials, flag, L.g, fg);
+        hipLaunchKernelGGL((k_readout<3, float>), grid, block, 0, L.stream, (const float*)cur, (float*)rho, (float*)u, partials, flag, L.g, fg, rho_max);
     else
-        hipLaunchKernelGGL((k_readout<3, double>), grid, block, 0, L.stream, (const double*)cur, (double*)rho, (double*)u, partials, flag, L.g, fg);
+        hipLaunchKernelGGL((k_readout<3, double>), grid, block, 0, L.stream, (const double*)cur, (double*)rho, (double*)u, partials, flag, L.g, fg, rho_max);
     return hipGetLastError();
 }
 

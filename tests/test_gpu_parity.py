@@ -516,3 +516,47 @@ def test_fp64_pressure_above_p0_branch(D):
     assert rel_max(rho_g, rho_o) < 1e-12 and rel_max(u_g, u_o) < 1e-12
     m = velocity_map(E.elmrt_velocities(p.lattice), D)
     np.testing.assert_allclose(f_g.T, f[:, m], rtol=0, atol=1e-13 * np.abs(f).max())
+
+
+def test_compensated_sums_large_grid():
+    """The library's global sums (compensated per thread, across wavefront
+    lanes, wavefronts and workgroups) on a 128^3 FP64 impact state against
+    the oracle's Neumaier sums in cell order: within 4 ulps of the total
+    (sum rho, sum rho u_z) or of the sum of magnitudes (the components that
+    cancel by symmetry)."""
+    from dataclasses import replace
+    w = replace(W.impact_job(3, 128, 1000, 0.04, 0), precision=1)
+    rho0, u0 = W.initial_fields(w)
+    say("[gpu] 128^3 FP64 sums")
+    sim = E.Simulation(E.params_for(w))
+    sim.init_fields(rho0, u0)
+    rho_g, u_g, s_g = sim.read_macros()
+    sim.close()
+    p = oracle_params(w)
+    f = O.init_fluid(p, rho0, u0)
+    rho_o, u_o, s_o = O.macros(p, f)
+    mags = [np.abs(rho_o).sum()] + [np.abs(rho_o * u_o[a]).sum() for a in range(3)]
+    eps = np.finfo(np.float64).eps
+    for k in range(4):
+        say(f"sum {k}: gpu {s_g[k]!r} oracle {s_o[k]!r} |diff|/mag {abs(s_g[k] - s_o[k]) / mags[k]:.2e}")
+        assert abs(s_g[k] - s_o[k]) <= 4 * eps * mags[k]
+
+
+def test_unstable_flag_beyond_the_pressure_pole():
+    """A uniform state at or beyond 1/b, the pole of the Peng-Robinson
+    pressure (Sec. 3.1), raises the sticky instability flag on the first step
+    (its force is zero, so nothing else would); just below 1/b it stays clear
+    and the mass is kept."""
+    w = W.STATIC_DROP_FP64.scaled(n=(40, 36), radius=9.0, film=0.0, centre=(20.0, 18.0), name="beyond-1/b")
+    b = w.eos["eos_b"]
+    for rho0, unstable in ((0.95 / b, False), (1.05 / b, True)):
+        sim = E.Simulation(E.params_for(w))
+        sim.init_fields(np.full(w.N, rho0), np.zeros((2, w.N)))
+        sim.step(1)
+        if unstable:
+            with pytest.raises(E.ElmrtUnstable):
+                sim.read_macros()
+        else:
+            _, _, sums = sim.read_macros()
+            assert abs(sums[0] / (rho0 * w.N) - 1) < 1e-14
+        sim.close()
