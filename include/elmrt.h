@@ -120,6 +120,24 @@ elmrt_status elmrt_step_timed(elmrt_sim* s, int64_t nsteps, double ms[2]);
  * Sec. 3.1), has been seen by a step or a read-out. */
 elmrt_status elmrt_read_macros(elmrt_sim* s, double* rho, double* u, double* sums);
 
+/* For callers that cannot allocate memory or synchronise the host -- code
+ * under HIP graph capture, serving loops that poll the diagnostics of
+ * resident simulations -- the sums of elmrt_read_macros and the instability
+ * flag, left in device memory.  Enqueues on the sim's stream, without
+ * waiting: dev_sums[0..3] (device FP64) receives [sum rho, sum rho u_x,
+ * sum rho u_y, sum rho u_z] of the current state, bitwise equal to the sums
+ * elmrt_read_macros returns for it, and *dev_flag (device, may be NULL) the
+ * instability flag word (nonzero: unstable).  No field is written; the host
+ * allocates nothing and the library calls no hipMalloc.  The partial sums go
+ * to a static device array of the library (one per device, 64 KiB: the 1024
+ * workgroup partials of the reduction, for any grid the library accepts).
+ * The sim's device must be current (else ELMRT_E_INVALID).  Calls on one
+ * device share that array: calls enqueued on different streams that may run
+ * at the same time race; order them (one stream, or events).  ELMRT_E_STATE
+ * before elmrt_init_fields; ELMRT_E_DEVICE if the array's device address
+ * cannot be looked up. */
+elmrt_status elmrt_read_sums_noalloc(elmrt_sim* s, double* dev_sums, uint32_t* dev_flag);
+
 /* Fluid velocity u + F dt/(2 rho) of the exact-difference forcing (Sec. 2.3,
  * F on the read-out density) at time t, u[D][N] FP64 host.  In a resting
  * two-phase state the bare velocity of elmrt_read_macros equals -F/(2 rho)

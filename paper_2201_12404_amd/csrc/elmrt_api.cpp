@@ -37,7 +37,7 @@ elmrt_status hip_fail(hipError_t e, const char* what)
 }
 
 constexpr size_t kAlign = 256;
-constexpr int kReadBlocks = 1024;
+constexpr int kReadBlocks = elmrt::kReadoutBlocks;
 
 size_t align_up(size_t v) { return (v + kAlign - 1) / kAlign * kAlign; }
 
@@ -218,6 +218,7 @@ struct elmrt_sim {
     unsigned* flag;
     double* partials;
     bool initialised;
+    int device;         // the device current at elmrt_create
     int tx, ty, tm;
     elmrt::Phys<double> ph;
     elmrt::Launch L;
@@ -275,6 +276,7 @@ elmrt_status elmrt_create(const elmrt_params* p, void* ws, size_t ws_bytes, void
     s->flag = (unsigned*)(s->ws + lay.flag);
     s->partials = (double*)(s->ws + lay.partials);
     s->initialised = false;
+    if (hipGetDevice(&s->device) != hipSuccess) s->device = -1;
     s->tx = 64;
     s->ty = s->D == 3 ? 4 : 1;
     s->tm = 0;   // automatic marching depth (auto_depth)
@@ -482,6 +484,25 @@ elmrt_status elmrt_read_fluid_velocity(elmrt_sim* s, double* u)
 {
     if (!u) return fail(ELMRT_E_INVALID, "u is NULL");
     return read_impl(s, nullptr, u, nullptr, true);
+}
+
+elmrt_status elmrt_read_sums_noalloc(elmrt_sim* s, double* dev_sums, uint32_t* dev_flag)
+{
+    if (!s || !dev_sums) return fail(ELMRT_E_INVALID, "NULL argument");
+    if (!s->initialised) return fail(ELMRT_E_STATE, "elmrt_init_fields has not been called");
+    int dev = -1;
+    hipError_t e = hipGetDevice(&dev);
+    if (e != hipSuccess) return hip_fail(e, "hipGetDevice");
+    if (dev != s->device) return fail(ELMRT_E_INVALID, "the simulation's device must be current");
+    double* scratch = nullptr;
+    int capacity = 0;
+    if ((e = elmrt::readout_scratch(&scratch, &capacity)) != hipSuccess) return hip_fail(e, "hipGetSymbolAddress(scratch)");
+    if (kReadBlocks > capacity) return fail(ELMRT_E_INVALID, "read-out reduction larger than the device scratch");
+    e = elmrt::launch_readout(s->L, s->buf[s->cur], nullptr, nullptr, scratch, kReadBlocks, s->flag, 1.0 / s->ph.b);
+    if (e != hipSuccess) return hip_fail(e, "readout kernel");
+    e = elmrt::launch_finish_sums(scratch, kReadBlocks, s->flag, dev_sums, dev_flag, s->stream);
+    if (e != hipSuccess) return hip_fail(e, "sums kernel");
+    return ELMRT_OK;
 }
 
 elmrt_status elmrt_read_populations(elmrt_sim* s, double* f)

@@ -89,6 +89,20 @@ hipError_t launch_init(const Launch& L, const double* rho0, const double* u0, vo
 hipError_t launch_readout(const Launch& L, const void* cur, void* rho, void* u, double* partials,
                           int nblocks, unsigned* flag, double rho_max);
 
+// Blocks of every read-out reduction, and the devices a process may use.
+constexpr int kReadoutBlocks = 1024;
+constexpr int kMaxDevices = 64;
+
+// Address, on the current device, of the library's static device scratch for
+// the partial sums of one read-out (capacity in blocks of k_readout); looked
+// up once per device.
+hipError_t readout_scratch(double** out, int* capacity_blocks);
+
+// sums[0..3] = merge of nblocks (sum, correction) pairs of partials, in block
+// order; *flag_out = *flag when flag_out is not NULL (device pointers).
+hipError_t launch_finish_sums(const double* partials, int nblocks, const unsigned* flag, double* sums,
+                              unsigned* flag_out, hipStream_t stream);
+
 // f_i(r, t) = pulled populations, written to out[i*N + cell].
 hipError_t launch_pull(const Launch& L, const void* cur, void* out);
 

@@ -37,6 +37,8 @@
 #include <math.h>
 #include <stdint.h>
 
+#include <mutex>
+
 namespace elmrt {
 namespace {
 
@@ -1273,6 +1275,26 @@ __global__ __launch_bounds__(256) void k_readout(const T* __restrict__ cur, T* _
     }
 }
 
+// Merge of the per-block (sum, correction) pairs of k_readout, in block
+// order, one quantity per thread: sums[k] = the compensated total of quantity
+// k; flag_out (if not NULL) receives the instability flag.  The same
+// arithmetic, in the same order, as the host merge of elmrt_read_macros.
+__global__ __launch_bounds__(64) void k_finish_sums(const double* __restrict__ partials, int nblocks,
+                                                    const unsigned* __restrict__ flag, double* __restrict__ sums,
+                                                    unsigned* __restrict__ flag_out)
+{
+    const int k = threadIdx.x;
+    if (k < 4) {
+        CSum t = {0.0, 0.0};
+        for (int b = 0; b < nblocks; ++b) {
+            csum_add(t, partials[b * 8 + 2 * k]);
+            t.c += partials[b * 8 + 2 * k + 1];
+        }
+        sums[k] = t.s + t.c;
+    }
+    if (k == 4 && flag_out) *flag_out = *flag;
+}
+
 template <int D, typename T>
 __global__ __launch_bounds__(256) void k_pull(const T* __restrict__ cur, T* __restrict__ out, Grid g, FlatGrid fg)
 {
@@ -1383,6 +1405,42 @@ hipError_t macro_batch_t(const BatchJob* jobs, int njobs, long long blocks, int 
 }
 
 }  // namespace
+
+// Device scratch of the no-allocation read-out (elmrt_read_sums_noalloc): the
+// (sum, correction) pairs of the kReadoutBlocks blocks of k_readout, 64 KiB.
+// Each device holds its own copy; host code reaches it only through the
+// address that hipGetSymbolAddress returns for the current device.
+static __device__ __align__(256) double scratch[kReadoutBlocks * 8];
+
+namespace {
+std::mutex g_scratch_mu;
+double* g_scratch_ptr[kMaxDevices] = {};
+}  // namespace
+
+hipError_t readout_scratch(double** out, int* capacity_blocks)
+{
+    int dev = 0;
+    hipError_t e = hipGetDevice(&dev);
+    if (e != hipSuccess) return e;
+    if (dev < 0 || dev >= kMaxDevices) return hipErrorInvalidDevice;
+    std::lock_guard<std::mutex> lock(g_scratch_mu);
+    if (!g_scratch_ptr[dev]) {
+        void* ptr = nullptr;
+        e = hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch));
+        if (e != hipSuccess) return e;
+        g_scratch_ptr[dev] = (double*)ptr;
+    }
+    *out = g_scratch_ptr[dev];
+    *capacity_blocks = kReadoutBlocks;
+    return hipSuccess;
+}
+
+hipError_t launch_finish_sums(const double* partials, int nblocks, const unsigned* flag, double* sums,
+                              unsigned* flag_out, hipStream_t stream)
+{
+    hipLaunchKernelGGL(k_finish_sums, dim3(1), dim3(64), 0, stream, partials, nblocks, flag, sums, flag_out);
+    return hipGetLastError();
+}
 
 bool collide_shape_supported(int D, int tx, int ty)
 {

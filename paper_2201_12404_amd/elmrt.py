@@ -61,6 +61,7 @@ _SIGS = {
     "elmrt_step_timed": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_int64, _dp]),
     "elmrt_read_macros": (ctypes.c_int, [ctypes.c_void_p, _dp, _dp, _dp]),
     "elmrt_read_populations": (ctypes.c_int, [ctypes.c_void_p, _dp]),
+    "elmrt_read_sums_noalloc": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p]),
     "elmrt_read_fluid_velocity": (ctypes.c_int, [ctypes.c_void_p, _dp]),
     "elmrt_velocities": (ctypes.c_int32, [ctypes.c_int32, ctypes.POINTER(ctypes.c_int32)]),
     "elmrt_coexistence": (ctypes.c_int, [ctypes.POINTER(elmrt_params), _dp, _dp, _dp]),
@@ -256,6 +257,12 @@ def elmrt_read_fluid_velocity(sim: int, N: int, D: int) -> np.ndarray:
         raise err
     _check(st)
     return u
+
+
+def elmrt_read_sums_noalloc(sim: int, dev_sums_ptr: int, dev_flag_ptr: int = 0) -> None:
+    """Enqueue the compensated sums (4 FP64 at dev_sums_ptr) and the flag word
+    (uint32 at dev_flag_ptr, or 0 for none) into device memory; no wait."""
+    _check(lib().elmrt_read_sums_noalloc(sim, dev_sums_ptr, dev_flag_ptr or None))
 
 
 def elmrt_read_populations(sim: int, Q: int, N: int) -> np.ndarray:
