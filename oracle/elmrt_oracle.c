@@ -41,6 +41,9 @@
  *       <= 0 or <dh|dh> <= eps^2 rho, eps = 2^-53.
  *   R14 nu is interpolated linearly in rho between nu_v at rho_v and nu_l at
  *       rho_l, clamped outside.
+ *   Optional readings (ora_params): trace_in_s puts the trace in s instead
+ *   (R6), phi_half_force takes the fluid velocity u + F/(2 rho) in the flux of
+ *   Phi instead of the bare one (R4); g adds a uniform body force rho g to F.
  *   R16 the initial state is the equilibrium at the bare velocity that gives
  *       the prescribed fluid velocity u + F/(2 rho) (ora_init_fluid); starting
  *       at bare u = 0 instead gives every interface an inward impulse F/2.
@@ -56,7 +59,13 @@
  *   polynomial fields, exact-in-roundoff mass and momentum conservation,
  *   invariance of uniform states, mirror symmetry, brute-force Maxwell against
  *   the closed-form chemical-potential condition, flat-interface coexistence,
- *   Laplace-law pressure jumps and the bulk value 2/(omega gamma) = 1.
+ *   Laplace-law pressure jumps and the bulk value 2/(omega gamma) = 1; the
+ *   viscosity of each density from shear-wave decay (R14 and omega(nu)), walls
+ *   against a mirrored doubled periodic grid (R15), the psi term above P0 (R3),
+ *   Phi in zeta* (Sec. 2.2), Poiseuille flow between the half-way walls under
+ *   a body force, the continuum limit of the width that kappa_for_width gives,
+ *   the viscosity-independent coexistence of the fluid-velocity Phi, and the
+ *   trace-in-s split against an explicit inverse.
  */
 #include "elmrt_oracle.h"
 
@@ -297,7 +306,7 @@ static void tensor_duals(int D, const double* u, double* Dt)
  * remaining (trace + higher) moments of the modified basis about u.  Each
  * part keeps its own moments a_k, goes back to tensor moments with the
  * inverse of the basis modification, then to populations with the duals. */
-void ora_split(int D, const double* u, const double* f, double* k, double* s, double* h)
+void ora_split(int D, int trace_in_s, const double* u, const double* f, double* k, double* s, double* h)
 {
     int Q = ora_Q(D);
     const double* Tinv = g_Tinv[D - 2];
@@ -309,7 +318,7 @@ void ora_split(int D, const double* u, const double* f, double* k, double* s, do
         double am[27], bm[27];
         for (int m = 0; m < Q; ++m) {
             int c = ora_moment_class(D, m);
-            int part = (c == 0) ? 0 : (c == 1 ? 1 : 2);
+            int part = (c == 0) ? 0 : (c == 1 || (c == 2 && trace_in_s) ? 1 : 2);
             am[m] = (part == cls) ? a[m] : 0.0;
         }
         for (int t = 0; t < Q; ++t) {
@@ -327,7 +336,7 @@ void ora_split(int D, const double* u, const double* f, double* k, double* s, do
 
 /* --------------------------------------------------------------- collision */
 
-void ora_collide(int D, int collision, double omega, const double* f, const double* F,
+void ora_collide(int D, int collision, int trace_in_s, double omega, const double* f, const double* F,
                  const double* Phi, double* fpost, double* gamma_out, int* fallback_out)
 {
     int Q = ora_Q(D);
@@ -345,8 +354,8 @@ void ora_collide(int D, int collision, double omega, const double* f, const doub
     ora_extended_equilibrium(D, rho, u, F, Phi, fstar);
 
     double k[27], s[27], h[27], keq[27], seq[27], heq[27];
-    ora_split(D, u, f, k, s, h);
-    ora_split(D, u, feq, keq, seq, heq);
+    ora_split(D, trace_in_s, u, f, k, s, h);
+    ora_split(D, trace_in_s, u, feq, keq, seq, heq);
 
     double gamma = 2.0;
     int fallback = 0;
@@ -508,6 +517,38 @@ int ora_maxwell(double a, double b, double R, double acentric, double Tr,
     return 0;
 }
 
+/* Square-gradient capillarity (textbook van der Waals theory, not from the
+ * paper): in a flat interface (kappa/2) rho'^2 = omega(rho), the excess grand
+ * potential density omega(rho) = rho int_{rho_v}^{rho} (P - P_sat)/s^2 ds, so the
+ * steepest gradient is sqrt(2 max omega / kappa) and the width W = (rho_l -
+ * rho_v) / max|rho'| of Sec. 3.1.1 fixes kappa.  omega is accumulated by
+ * Simpson's rule over a fine grid of [rho_v, rho_l] and its maximum taken on
+ * that grid. */
+int ora_kappa_for_width(double a, double b, double R, double acentric, double Tr, double W,
+                        double* kappa)
+{
+    double rv, rl, ps;
+    if (!(W > 0.0) || ora_maxwell(a, b, R, acentric, Tr, &rv, &rl, &ps) != 0) return -1;
+    maxwell_ctx m;
+    m.aal = a * ora_alpha(acentric, Tr);
+    m.b = b;
+    m.RT = R * Tr * ora_Tc(a, b, R);
+    m.psat = ps;
+    const int NG = 20000;             /* grid intervals, each integrated by Simpson */
+    const double h = (rl - rv) / NG;
+    double integral = 0.0, best = 0.0;
+    for (int k = 0; k < NG; ++k) {
+        const double r0 = rv + h * k, r1 = r0 + h, rm = 0.5 * (r0 + r1);
+        /* int (P - P_sat)/s^2 over [r0, r1] = -int (P_sat - P)/s^2 */
+        integral -= h / 6.0 * (maxwell_integrand(&m, r0) + 4.0 * maxwell_integrand(&m, rm) +
+                               maxwell_integrand(&m, r1));
+        const double om = r1 * integral;
+        if (om > best) best = om;
+    }
+    *kappa = 2.0 * best * W * W / ((rl - rv) * (rl - rv));
+    return 0;
+}
+
 /* omega = dt / (rho nu / P0 + dt/2) with P0 = rho cs^2 (Sec. 2), nu(rho) by R14. */
 double ora_omega(const ora_params* p, double rho)
 {
@@ -580,7 +621,11 @@ static double psi_of(const ora_params* p, double rho)
     return (P > P0) ? sqrt(P - P0) : sqrt(P0 - P);
 }
 
-/* q_a = rho u_a (u_a^2 + 3 P0/rho - 3 cs^2), the flux differentiated in Phi (Sec. 2.2) */
+static void force_at(const grid_ctx* C, const int x[3], double F[3], int* p_above);
+
+/* q_a = rho u_a (u_a^2 + 3 P0/rho - 3 cs^2), the flux differentiated in Phi
+ * (Sec. 2.2); u is the bare velocity (R4), or with phi_half_force the fluid
+ * velocity u + F dt/(2 rho) */
 static double q_of_cell(const grid_ctx* C, int64_t idx, int a)
 {
     if (C->q) return C->q[(int64_t)a * ncells(C->p) + idx];
@@ -593,6 +638,15 @@ static double q_of_cell(const grid_ctx* C, int64_t idx, int a)
         j += c[a] * fc[i];
     }
     double u = j / rho;
+    if (C->p->phi_half_force) {
+        int x[3];
+        x[0] = (int)(idx % C->p->n[0]);
+        x[1] = (int)((idx / C->p->n[0]) % C->p->n[1]);
+        x[2] = (int)(idx / ((int64_t)C->p->n[0] * C->p->n[1]));
+        double F[3];
+        force_at(C, x, F, NULL);
+        u += F[a] / (2.0 * rho);
+    }
     double P0 = rho * CS2;
     return rho * u * (u * u + 3.0 * P0 / rho - 3.0 * CS2);
 }
@@ -634,7 +688,8 @@ static void force_at(const grid_ctx* C, const int x[3], double F[3], int* p_abov
         }
     }
     for (int a = 0; a < 3; ++a) F[a] = 0.0;
-    for (int a = 0; a < D; ++a) F[a] = sign * 2.0 * psi_r * G[a] + p->kappa * rho * K[a];
+    /* psi and capillary terms (Sec. 2.3), and the uniform body force rho g */
+    for (int a = 0; a < D; ++a) F[a] = sign * 2.0 * psi_r * G[a] + p->kappa * rho * K[a] + rho * p->g[a];
     if (p_above) *p_above = (P > P0);
 }
 
@@ -656,7 +711,7 @@ static void post_collision_at(const grid_ctx* C, const int x[3], double* fpost, 
         /* Phi_aa = (1 - omega/2) dt d_a q_a, central difference (reading R5) */
         Phi[a] = (1.0 - 0.5 * omega) * 0.5 * (q_at(C, xp, a) - q_at(C, xm, a));
     }
-    ora_collide(D, p->collision, omega, C->f + idx * C->Q, F, Phi, fpost, gamma, fallback);
+    ora_collide(D, p->collision, p->trace_in_s, omega, C->f + idx * C->Q, F, Phi, fpost, gamma, fallback);
 }
 
 static int check_params(const ora_params* p)
@@ -742,13 +797,15 @@ int ora_step(const ora_params* p, double* f, int64_t nsteps, ora_stats* st, doub
     double gmin = INFINITY, gmax = -INFINITY;
     for (int64_t step = 0; step < nsteps; ++step) {
         int last = (step == nsteps - 1);
-        /* A: moments and the flux q of every cell */
+        /* A: moments and the flux q of every cell (the fluid velocity of
+         * phi_half_force needs the force, hence every density first) */
         grid_ctx C0 = {p, Q, f, NULL, NULL};
 #pragma omp parallel for schedule(static)
-        for (int64_t c = 0; c < N; ++c) {
-            rho[c] = rho_of_cell(&C0, c);
-            for (int a = 0; a < 3; ++a) q[(int64_t)a * N + c] = (a < D) ? q_of_cell(&C0, c, a) : 0.0;
-        }
+        for (int64_t c = 0; c < N; ++c) rho[c] = rho_of_cell(&C0, c);
+        grid_ctx CA = {p, Q, f, rho, NULL};
+#pragma omp parallel for schedule(static)
+        for (int64_t c = 0; c < N; ++c)
+            for (int a = 0; a < 3; ++a) q[(int64_t)a * N + c] = (a < D) ? q_of_cell(&CA, c, a) : 0.0;
         /* B: force, Phi and collision of every cell */
         grid_ctx C = {p, Q, f, rho, q};
         int64_t la = 0, lf = 0, lb = 0;

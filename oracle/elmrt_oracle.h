@@ -32,6 +32,11 @@ typedef struct {
     double kappa;       /* capillarity coefficient kappa~ = kappa * dr^2 */
     double nu_l, nu_v;  /* kinematic viscosities of liquid and vapour */
     double rho_l, rho_v;/* densities between which nu is interpolated */
+    double g[3];        /* uniform body acceleration: F += rho g */
+    int32_t trace_in_s; /* 0: the trace of the second moments belongs to h (reading R6);
+                           1: to s, relaxed with omega like the deviatoric stress */
+    int32_t phi_half_force; /* 0: the flux q of Phi uses the bare velocity (R4);
+                               1: the fluid velocity u + F dt/(2 rho) */
 } ora_params;
 
 typedef struct {
@@ -53,14 +58,15 @@ void   ora_equilibrium(int D, double rho, const double* u, double* feq);
 void   ora_extended_equilibrium(int D, double rho, const double* u, const double* F,
                                 const double* Phi, double* fstar);
 
-/* Modified central Hermite moments and the k + s + h split. */
+/* Modified central Hermite moments and the k + s + h split; trace_in_s
+ * selects the part that takes the trace of the second moments (0: h). */
 int    ora_moment_class(int D, int k);   /* 0 conserved, 1 stress, 2 trace, 3 higher */
 void   ora_moments(int D, const double* u, const double* f, double* a);
-void   ora_split(int D, const double* u, const double* f, double* k, double* s, double* h);
+void   ora_split(int D, int trace_in_s, const double* u, const double* f, double* k, double* s, double* h);
 
 /* One cell's collision: f -> post-collision populations (not yet streamed).
  * F, Phi: force and diagonal correction.  gamma_out may be NULL. */
-void   ora_collide(int D, int collision, double omega, const double* f, const double* F,
+void   ora_collide(int D, int collision, int trace_in_s, double omega, const double* f, const double* F,
                    const double* Phi, double* fpost, double* gamma_out, int* fallback_out);
 
 /* Peng-Robinson thermodynamics. */
@@ -69,6 +75,11 @@ double ora_alpha(double acentric, double Tr);
 double ora_pressure(const ora_params* p, double rho);
 int    ora_maxwell(double a, double b, double R, double acentric, double Tr,
                    double* rho_v, double* rho_l, double* p_sat);
+/* Square-gradient capillarity for an interface of width W = (rho_l - rho_v) /
+ * max |d rho/dx|: kappa~ = 2 max(omega) W^2 / (rho_l - rho_v)^2 with the excess
+ * grand potential omega(rho) = rho int_{rho_v}^{rho} (P(s) - P_sat)/s^2 ds. */
+int    ora_kappa_for_width(double a, double b, double R, double acentric, double Tr, double W,
+                           double* kappa);
 
 /* Relaxation rate at density rho. */
 double ora_omega(const ora_params* p, double rho);

@@ -48,6 +48,9 @@ class _Params(ctypes.Structure):
         ("kappa", ctypes.c_double),
         ("nu_l", ctypes.c_double), ("nu_v", ctypes.c_double),
         ("rho_l", ctypes.c_double), ("rho_v", ctypes.c_double),
+        ("g", ctypes.c_double * 3),
+        ("trace_in_s", ctypes.c_int32),
+        ("phi_half_force", ctypes.c_int32),
     ]
 
 
@@ -80,8 +83,8 @@ def lib():
         L.ora_moment_class.argtypes = [ctypes.c_int, ctypes.c_int]
         L.ora_moment_class.restype = ctypes.c_int
         L.ora_moments.argtypes = [ctypes.c_int, _dp, _dp, _dp]
-        L.ora_split.argtypes = [ctypes.c_int, _dp, _dp, _dp, _dp, _dp]
-        L.ora_collide.argtypes = [ctypes.c_int, ctypes.c_int, ctypes.c_double, _dp, _dp, _dp, _dp,
+        L.ora_split.argtypes = [ctypes.c_int, ctypes.c_int, _dp, _dp, _dp, _dp, _dp]
+        L.ora_collide.argtypes = [ctypes.c_int, ctypes.c_int, ctypes.c_int, ctypes.c_double, _dp, _dp, _dp, _dp,
                                   _dp, ctypes.POINTER(ctypes.c_int)]
         L.ora_Tc.argtypes = [ctypes.c_double] * 3
         L.ora_Tc.restype = ctypes.c_double
@@ -91,6 +94,8 @@ def lib():
         L.ora_pressure.restype = ctypes.c_double
         L.ora_maxwell.argtypes = [ctypes.c_double] * 5 + [_dp, _dp, _dp]
         L.ora_maxwell.restype = ctypes.c_int
+        L.ora_kappa_for_width.argtypes = [ctypes.c_double] * 6 + [_dp]
+        L.ora_kappa_for_width.restype = ctypes.c_int
         L.ora_omega.argtypes = [ctypes.POINTER(_Params), ctypes.c_double]
         L.ora_omega.restype = ctypes.c_double
         L.ora_force_field.argtypes = [ctypes.POINTER(_Params), _dp, _dp]
@@ -173,20 +178,20 @@ def moments(D, u, f):
     return a
 
 
-def split(D, u, f):
+def split(D, u, f, trace_in_s: int = 0):
     Q = Q_of(D)
     k, s, h = np.zeros(Q), np.zeros(Q), np.zeros(Q)
-    lib().ora_split(D, _ptr(_vec(u, D)), _ptr(np.ascontiguousarray(f, dtype=np.float64)),
+    lib().ora_split(D, int(trace_in_s), _ptr(_vec(u, D)), _ptr(np.ascontiguousarray(f, dtype=np.float64)),
                     _ptr(k), _ptr(s), _ptr(h))
     return k, s, h
 
 
-def collide(D, collision, omega, f, F, Phi):
+def collide(D, collision, omega, f, F, Phi, trace_in_s: int = 0):
     """One cell's collision; returns (post-collision populations, gamma, fell_back)."""
     out = np.zeros(Q_of(D))
     g = ctypes.c_double()
     fb = ctypes.c_int()
-    lib().ora_collide(D, int(collision), float(omega),
+    lib().ora_collide(D, int(collision), int(trace_in_s), float(omega),
                       _ptr(np.ascontiguousarray(f, dtype=np.float64)),
                       _ptr(_vec(F, D)), _ptr(_vec(Phi, D)), _ptr(out), ctypes.byref(g), ctypes.byref(fb))
     return out, g.value, bool(fb.value)
@@ -212,6 +217,15 @@ def maxwell(a, b, R, acentric, Tr):
     return rv.value, rl.value, ps.value
 
 
+def kappa_for_width(a, b, R, acentric, Tr, W):
+    """Square-gradient kappa~ of an interface of width W (brute force)."""
+    k = ctypes.c_double()
+    rc = lib().ora_kappa_for_width(a, b, R, acentric, Tr, W, ctypes.byref(k))
+    if rc != 0:
+        raise ValueError(f"ora_kappa_for_width failed ({rc})")
+    return k.value
+
+
 # ------------------------------------------------------------------ grid
 
 
@@ -231,6 +245,9 @@ class Params:
     nu_v: float = 0.02
     rho_l: float = 0.0
     rho_v: float = 0.0
+    g: tuple = (0.0, 0.0, 0.0)      # uniform body acceleration
+    trace_in_h: bool = True         # reading R6; False puts the trace in s
+    phi_velocity: int = 0           # reading R4: 0 bare u, 1 fluid velocity u + F/(2 rho)
 
     def c(self) -> _Params:
         p = _Params()
@@ -244,6 +261,11 @@ class Params:
         p.a, p.b, p.R, p.acentric, p.Tr = self.a, self.b, self.R, self.acentric, self.Tr
         p.kappa = self.kappa
         p.nu_l, p.nu_v, p.rho_l, p.rho_v = self.nu_l, self.nu_v, self.rho_l, self.rho_v
+        g = list(self.g) + [0.0] * (3 - len(self.g))
+        for k in range(3):
+            p.g[k] = float(g[k])
+        p.trace_in_s = 0 if self.trace_in_h else 1
+        p.phi_half_force = int(self.phi_velocity)
         return p
 
     @property

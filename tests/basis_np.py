@@ -67,8 +67,9 @@ def matrix(D: int, u):
     return labs, np.stack([moment_row(D, l, u) for l in labs])
 
 
-def category(lab) -> str:
-    """conserved / stress / h (trace and higher orders go to h)."""
+def category(lab, trace_in_s: bool = False) -> str:
+    """conserved / stress / h (the trace goes to h, or to s with trace_in_s;
+    higher orders go to h)."""
     if isinstance(lab, tuple):
         o = sum(lab)
         if o <= 1:
@@ -76,14 +77,16 @@ def category(lab) -> str:
         if o == 2:
             return "stress"            # off-diagonal second order
         return "h"
-    return "h" if lab == "trace" else "stress"
+    if lab == "trace":
+        return "stress" if trace_in_s else "h"
+    return "stress"
 
 
-def project(D: int, u, f, cat: str) -> np.ndarray:
+def project(D: int, u, f, cat: str, trace_in_s: bool = False) -> np.ndarray:
     """Projection of f on the moments of one category, by explicit inversion."""
     labs, M = matrix(D, u)
     a = M @ f
-    mask = np.array([category(l) == cat for l in labs], dtype=float)
+    mask = np.array([category(l, trace_in_s) == cat for l in labs], dtype=float)
     return np.linalg.solve(M, mask * a)
 
 

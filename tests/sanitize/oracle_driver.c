@@ -12,7 +12,7 @@
 
 #include "../../oracle/elmrt_oracle.h"
 
-static int run(int D, int nx, int ny, int nz, int bcz, int collision)
+static int run(int D, int nx, int ny, int nz, int bcz, int collision, int options)
 {
     ora_params p;
     memset(&p, 0, sizeof p);
@@ -22,6 +22,14 @@ static int run(int D, int nx, int ny, int nz, int bcz, int collision)
     p.collision = collision;
     p.a = 0.003; p.b = 0.095; p.R = 1.0; p.acentric = 0.344; p.Tr = 0.8;
     p.kappa = 0.004; p.nu_l = 0.05; p.nu_v = 0.1;
+    if (options) {
+        /* body force and the alternative readings of the trace and of Phi */
+        p.g[0] = 1e-5; p.g[D - 1] = -2e-5;
+        p.trace_in_s = 1;
+        p.phi_half_force = 1;
+        double k;
+        if (ora_kappa_for_width(p.a, p.b, p.R, p.acentric, p.Tr, 5.0, &k) != 0 || !(k > 0.0)) return 1;
+    }
     double rv, rl, ps;
     if (ora_maxwell(p.a, p.b, p.R, p.acentric, p.Tr, &rv, &rl, &ps) != 0) return 1;
     p.rho_l = rl; p.rho_v = rv;
@@ -74,12 +82,13 @@ int main(void)
 {
     int bad = 0;
     ora_set_threads(2);
-    for (int coll = 0; coll < 2; ++coll) {
-        bad |= run(2, 20, 14, 1, 0, coll);
-        bad |= run(2, 20, 14, 1, 1, coll);
-        bad |= run(3, 12, 10, 14, 0, coll);
-        bad |= run(3, 12, 10, 14, 1, coll);
-    }
+    for (int coll = 0; coll < 2; ++coll)
+        for (int opt = 0; opt < 2; ++opt) {
+            bad |= run(2, 20, 14, 1, 0, coll, opt);
+            bad |= run(2, 20, 14, 1, 1, coll, opt);
+            bad |= run(3, 12, 10, 14, 0, coll, opt);
+            bad |= run(3, 12, 10, 14, 1, coll, opt);
+        }
     if (bad) fprintf(stderr, "oracle driver: FAILED\n");
     return bad;
 }

@@ -265,3 +265,121 @@ def test_phi_correction_enters_the_extended_equilibrium(D, n):
         expect[:, i] = g.reshape(-1)
     np.testing.assert_allclose(f, expect, rtol=0, atol=1e-15)
     assert np.abs(phi).max() > 1e-5
+
+
+# --------------------------------------------------------------- body force
+
+
+@pytest.mark.parametrize("D,nu,collision", [(2, 1.0 / 6.0, 0), (2, 1.0 / 6.0, 1), (2, 0.1, 0), (3, 0.1, 0)])
+def test_body_force_poiseuille_between_halfway_walls(D, nu, collision):
+    """A uniform body force rho g along x between walls (half-way bounce-back,
+    reading R15) drives plane Poiseuille flow whose fluid velocity u + F/(2
+    rho) is the parabola g/(2 nu) (y + 1/2)(H - 1/2 - y): the walls sit half a
+    cell outside the first and last nodes.  Within 1 % of the peak (the
+    measured departure is 0.15-0.5 %; a wall on the nodes or a force of the
+    wrong size misses by > 10 %)."""
+    H, g = 16, 1e-5
+    n = (4, H, 1) if D == 2 else (4, 4, H)
+    bc = (0, 1, 0) if D == 2 else (0, 0, 1)
+    p = O.Params(D=D, n=n, bc=bc, collision=collision, kappa=0.03, nu_l=nu, nu_v=nu, g=(g, 0.0, 0.0))
+    rho0 = 0.15
+    f = O.init_fluid(p, np.full(p.N, rho0), np.zeros((D, p.N)))
+    O.step(p, f, int(6 * H * H / nu / 10))
+    r, u, _ = O.macros(p, f)
+    assert np.abs(r - rho0).max() < 1e-6 * rho0
+    ux = u[0] + g / 2.0
+    wall_axis = _grid(D, n)[D - 1]
+    exact = g / (2 * nu) * (wall_axis + 0.5) * (H - 0.5 - wall_axis)
+    err = np.abs(ux - exact).max() / exact.max()
+    assert err < 0.01, err
+    assert np.abs(u[1:]).max() < 1e-5 * exact.max()
+
+
+# ------------------------------------------------------- kappa from a width
+
+
+def _slab(tr, W, nu=0.1, phi=0, steps=None, kappa=None):
+    """Liquid slab in vapour (EOS a = 0.003, b = 0.095), 1-D along x, tanh
+    interfaces of width W, run to equilibrium; returns (rho along x, rho_v,
+    rho_l of the Maxwell rule)."""
+    a, b = 0.003, 0.095
+    rv, rl, _ = O.maxwell(a, b, 1.0, 0.344, tr)
+    k = O.kappa_for_width(a, b, 1.0, 0.344, tr, W) if kappa is None else kappa
+    L = int(12 * W)
+    p = O.Params(D=2, n=(L, 3, 1), a=a, b=b, Tr=tr, kappa=k, nu_l=nu, nu_v=nu, phi_velocity=phi)
+    x = np.tile(np.arange(L, dtype=float), 3)
+    rho0 = rv + (rl - rv) * 0.5 * (np.tanh(2 * (x - L / 4) / W) - np.tanh(2 * (x - 3 * L / 4) / W))
+    f = O.init_fluid(p, rho0, np.zeros((2, p.N)))
+    O.step(p, f, steps if steps is not None else int(20 * W * W))
+    r, _, _ = O.macros(p, f)
+    return r[:L], rv, rl
+
+
+def test_kappa_for_width_vanishing_potential_at_coexistence():
+    """The excess grand potential behind kappa~(W) vanishes at both
+    coexistence densities (Maxwell's equal areas), so kappa~ scales as W^2
+    exactly and is positive."""
+    for tr in (0.6, 0.8, 0.9):
+        k1 = O.kappa_for_width(0.003, 0.095, 1.0, 0.344, tr, 5.0)
+        k2 = O.kappa_for_width(0.003, 0.095, 1.0, 0.344, tr, 10.0)
+        assert k1 > 0 and abs(k2 / k1 - 4.0) < 1e-12
+
+
+@pytest.mark.slow
+def test_kappa_for_width_gives_that_width_in_the_continuum_limit():
+    """kappa~(W) is the square-gradient capillarity of an interface of width
+    W = (rho_l - rho_v) / max |d rho/dx| (Sec. 3.1.1).  The model's force
+    (Sec. 2.3) has the square-gradient equilibrium as its continuum limit, so
+    the converged width of a flat interface approaches W as W grows: the
+    measured ratios at W = 16 and 24 (1.18, 1.085 at T/Tc = 0.9) fall off as
+    W^-2, and their quadratic extrapolation is 1 within 2 %.  A kappa~ off by a
+    factor c would extrapolate to sqrt(c)."""
+    ratios = {}
+    for W in (16, 24):
+        r, _, _ = _slab(0.9, W)
+        grad = np.abs(np.roll(r, -1) - np.roll(r, 1)) / 2
+        ratios[W] = (r.max() - r.min()) / grad.max() / W
+    limit = (ratios[24] * 24 ** 2 - ratios[16] * 16 ** 2) / (24 ** 2 - 16 ** 2)
+    assert ratios[16] > ratios[24] > 1.0
+    assert abs(limit - 1.0) < 0.02, (ratios, limit)
+
+
+# ------------------------------------------------- readings R4 and R6
+
+
+def test_phi_with_fluid_velocity_makes_coexistence_independent_of_viscosity():
+    """Reading R4 and its alternative: at rest the bare velocity is -F/(2 rho)
+    near an interface, so with the bare velocity the flux of Phi, and the
+    vapour density it leaves, depend on nu; with the fluid velocity u + F/(2
+    rho) (phi_velocity = 1) the flux vanishes at rest and the coexistence no
+    longer depends on nu (flat interface, T/Tc = 0.6, nu = 0.1 and 0.03)."""
+    out = {}
+    for phi in (0, 1):
+        out[phi] = [(_slab(0.6, 6, nu=nu, phi=phi, steps=6000, kappa=O.kappa_for_width(0.003, 0.095, 1.0, 0.344, 0.6, 6)))
+                    for nu in (0.1, 0.03)]
+    rv_of = {phi: [r.min() / rv - 1 for r, rv, _ in out[phi]] for phi in out}
+    assert abs(rv_of[1][0] - rv_of[1][1]) < 0.003, rv_of
+    assert abs(rv_of[0][0] - rv_of[0][1]) > 0.05, rv_of
+    for phi in out:
+        for r, _, rl in out[phi]:
+            assert abs(r.max() / rl - 1) < 0.001
+
+
+@pytest.mark.parametrize("D", [2, 3])
+def test_trace_in_s_split_equals_explicit_projection(D):
+    """Reading R6 and its alternative: with trace_in_s the trace of the
+    second-order central moments moves from h to s; both splits equal the
+    projections by explicit inversion of the modified central Hermite basis
+    (Appendix A), and k + s + h = f either way."""
+    import basis_np as B
+    rng = np.random.default_rng(5)
+    for _ in range(5):
+        u = rng.uniform(-0.1, 0.1, D)
+        f = O.equilibrium(D, 1.3, u) * (1 + rng.uniform(-0.05, 0.05, 3 ** D))
+        for tis in (False, True):
+            k, s, h = O.split(D, u, f, trace_in_s=int(tis))
+            np.testing.assert_allclose(s, B.project(D, u, f, "stress", tis), atol=1e-14)
+            np.testing.assert_allclose(h, B.project(D, u, f, "h", tis), atol=1e-14)
+            np.testing.assert_allclose(k + s + h, f, atol=1e-14)
+        s0 = O.split(D, u, f, 0)[1]
+        assert np.abs(s - s0).max() > 1e-6
