@@ -159,33 +159,28 @@ def batched_vs_plain(steps: int = 2000, trial_steps: int = 4):
             "accuracy": "bitwise equal to the plain path (same kernels)"}
 
 
-def served_vs_plain(count: int, step_scale: float, pool_gib: float = 16.0, chunk: int = 200,
-                    fill: int = 4 << 20, policy: int = 1):
-    """The served impact stream (seeded Poisson arrivals, 20 jobs/s, D2Q9 and
-    D3Q27 drop impacts of mixed size, density ratio and speed), first 'count'
-    jobs with step counts scaled by 'step_scale'.  Served: arrivals replayed
-    in real time into the request loop (admission by footprint into a
-    'pool_gib' GiB pool, resident jobs advanced in shared batches of 'chunk'
-    steps, least remaining work first up to 'fill' cells per round).  Plain:
-    each job alone through the single-simulation path (upload, steps,
-    read-out); its FIFO completion times follow from the measured service
-    times and the same arrival times.  Latency = arrival to completion;
-    aggregate MLUPS = lattice updates / makespan (first arrival to last
-    completion) on both sides."""
-    import numpy as np
-    import torch
-
-    from paper_2201_12404_amd import elmrt as E
+def served_jobs(count: int, step_scale: float):
+    """The first 'count' jobs of the served impact stream (seeded Poisson
+    arrivals, 20 jobs/s, D2Q9 and D3Q27 drop impacts of mixed size, density
+    ratio and speed) with step counts scaled by 'step_scale', and their
+    initial fields."""
     from paper_2201_12404_amd import workloads as W
 
     stream = W.served_stream(count=count, rate=20.0, seed=0)
     jobs = [(t, w, max(1, int(round(w.steps * step_scale)))) for t, w in stream]
-    lu_total = sum(w.N * n for _, w, n in jobs)
+    return jobs, [W.initial_fields(w) for _, w, _ in jobs]
 
-    # plain: service times of each job alone
-    service = []
-    inputs = [W.initial_fields(w) for _, w, _ in jobs]
-    unstable = []
+
+def plain_fifo(jobs, inputs):
+    """Each job alone through the single-simulation path (upload, steps,
+    read-out), one after another; FIFO completion times follow from the
+    measured service times and the arrival times."""
+    import numpy as np
+    import torch
+
+    from paper_2201_12404_amd import elmrt as E
+
+    service, unstable = [], []
     for k, ((_, w, n), (rho0, u0)) in enumerate(zip(jobs, inputs)):
         sim = E.Simulation(E.params_for(w))
         torch.cuda.synchronize()
@@ -204,11 +199,22 @@ def served_vs_plain(count: int, step_scale: float, pool_gib: float = 16.0, chunk
     for (t, _, _), sv in zip(jobs, service):
         finish = max(finish, t) + sv
         lat.append(finish - t)
-    plain = {"p50_s": round(float(np.percentile(lat, 50)), 3), "p99_s": round(float(np.percentile(lat, 99)), 3),
-             "mlups": round(lu_total / finish / 1e6, 1), "makespan_s": round(finish, 3),
-             "busy_s": round(sum(service), 3), "unstable_jobs": unstable}
+    lu = sum(w.N * n for _, w, n in jobs)
+    return {"p50_s": round(float(np.percentile(lat, 50)), 3), "p99_s": round(float(np.percentile(lat, 99)), 3),
+            "mlups": round(lu / finish / 1e6, 1), "makespan_s": round(finish, 3),
+            "busy_s": round(sum(service), 3), "unstable_jobs": unstable}
 
-    # served: real-time replay of the arrivals
+
+def served_replay(jobs, inputs, policy: int, fill: int, chunk: int, pool_gib: float = 16.0):
+    """Arrivals replayed in real time into the request loop (admission by
+    footprint into a 'pool_gib' GiB pool, rounds of resident jobs up to 'fill'
+    cells in the scheduling 'policy' order, 'chunk' steps for the costliest
+    batch of a round).  Latency = arrival to completion; aggregate MLUPS =
+    lattice updates / makespan (first arrival to last completion)."""
+    import numpy as np
+
+    from paper_2201_12404_amd import elmrt as E
+
     srv = E.Server(pool_bytes=int(pool_gib * (1 << 30)), chunk_steps=chunk)
     srv.set_fill(fill)
     srv.set_policy(policy)
@@ -231,18 +237,32 @@ def served_vs_plain(count: int, step_scale: float, pool_gib: float = 16.0, chunk
         if q == 0 and r == 0 and k < len(jobs):
             time.sleep(max(0.0, min(0.01, jobs[k][0] - (time.monotonic() - t_start))))
     t_end = time.monotonic() - t_start
-    lat_s, evicted = [], []
+    lat, evicted = [], []
     for k, ((t, _, n), jid) in enumerate(zip(jobs, ids)):
         st, times, done = srv.job(jid)
-        lat_s.append(times[2] - (t_start + t))
+        lat.append(times[2] - (t_start + t))
         if done < n:
             evicted.append(k)   # went unstable: read out early
     srv.close()
-    served = {"p50_s": round(float(np.percentile(lat_s, 50)), 3), "p99_s": round(float(np.percentile(lat_s, 99)), 3),
-              "mlups": round(lu_total / t_end / 1e6, 1), "makespan_s": round(t_end, 3), "evicted_jobs": evicted}
+    lu = sum(w.N * n for _, w, n in jobs)
+    return {"policy": ["arrival", "least remaining work", "least remaining work, oldest first"][policy],
+            "fill_cells": fill, "chunk": chunk,
+            "p50_s": round(float(np.percentile(lat, 50)), 3), "p99_s": round(float(np.percentile(lat, 99)), 3),
+            "mlups": round(lu / t_end / 1e6, 1), "makespan_s": round(t_end, 3), "evicted_jobs": evicted}
+
+
+def served_vs_plain(count: int, step_scale: float, fill: int = 4 << 20, chunk: int = 200):
+    """Plain FIFO against the request loop in arrival order (the server's
+    default) and with least remaining work first, on the same jobs."""
+    jobs, inputs = served_jobs(count, step_scale)
+    lu = sum(w.N * n for _, w, n in jobs)
+    plain = plain_fifo(jobs, inputs)
+    served = served_replay(jobs, inputs, 0, fill, chunk)
+    print("[bench] served, least remaining work first", file=sys.stderr, flush=True)
+    served_lrw = served_replay(jobs, inputs, 1, fill, chunk)
     return {"workload": f"first {count} jobs of the served stream (seed 0, 20 jobs/s), steps x {step_scale}, "
-                        f"{lu_total:.3e} lattice updates, FP32",
-            "served": served, "plain": plain,
+                        f"{lu:.3e} lattice updates, FP32",
+            "served": served, "served_least_work_first": served_lrw, "plain": plain,
             "accuracy": "bitwise equal to the job run alone (tested)"}
 
 
@@ -270,8 +290,8 @@ def main():
     ap.add_argument("--tile", type=str, default="64,4,46", help="tx,ty,tm of the collision kernel")
     ap.add_argument("--autotune", action="store_true", help="let the library's autotuner pick the tiling")
     ap.add_argument("--no-batched", action="store_true", help="skip the batched and served comparisons")
-    ap.add_argument("--serve-jobs", type=int, default=24, help="jobs of the served stream to replay")
-    ap.add_argument("--serve-step-scale", type=float, default=0.1, help="scale of the served jobs' step counts")
+    ap.add_argument("--serve-jobs", type=int, default=200, help="jobs of the served stream to replay")
+    ap.add_argument("--serve-step-scale", type=float, default=0.25, help="scale of the served jobs' step counts")
     args = ap.parse_args()
 
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:

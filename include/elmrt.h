@@ -52,6 +52,15 @@ enum { ELMRT_D2Q9 = 0, ELMRT_D3Q27 = 1 };
 enum { ELMRT_FP32 = 0, ELMRT_FP64 = 1 };
 enum { ELMRT_ENTROPIC = 0, ELMRT_BGK = 1 };
 enum { ELMRT_PERIODIC = 0, ELMRT_WALL = 1 };
+/* Readings of points the paper leaves open (elmrt_params.readings, a bit set;
+ * 0 = the default reading of each). */
+enum {
+    ELMRT_READING_TRACE_IN_S = 1,        /* the trace of the second-order central moments relaxes
+                                            with omega as part of s; default: part of h, under
+                                            entropic control (Sec. 3.1.2, Appendix A) */
+    ELMRT_READING_PHI_FLUID_VELOCITY = 2 /* the flux q of Phi (Sec. 2.2) uses the fluid velocity
+                                            u + F dt/(2 rho); default: the bare u = sum c f / rho */
+};
 
 /* Problem statement.  struct_size must be sizeof(elmrt_params). */
 typedef struct {
@@ -67,16 +76,25 @@ typedef struct {
     int32_t  bc[3];          /* per axis: ELMRT_PERIODIC, or ELMRT_WALL (half-way
                                 bounce-back at both ends; stencil ghosts mirror
                                 the density about the wall plane) */
-    int32_t  reserved;       /* 0 */
+    int32_t  readings;       /* 0, or ELMRT_READING_* bits */
     /* Peng-Robinson equation of state (Sec. 3.1): a, b, R, acentric factor,
        and the temperature as T/Tc with Tc = 0.0778 a / (0.45724 b R). */
     double   eos_a, eos_b, eos_R, acentric, T_over_Tc;
-    double   kappa_tilde;    /* capillarity kappa~ = kappa dr^2 of the force stencil (Sec. 2.3), >= 0 */
+    double   kappa_tilde;    /* capillarity kappa~ = kappa dr^2 of the force stencil (Sec. 2.3), >= 0;
+                                with target_W > 0 it must be 0 and is derived from W */
     /* Kinematic viscosity nu (omega = 1/(3 nu + 1/2), Sec. 2): nu_vapour at
        rho <= rho_vapour, nu_liquid at rho >= rho_liquid, linear in between.
        With nu_liquid == nu_vapour the two densities are not used. */
     double   nu_liquid, nu_vapour;
     double   rho_liquid, rho_vapour;
+    /* Uniform body acceleration g: the force of Sec. 2 (F in the extended
+       equilibrium f*) gains rho g in every cell.  Components beyond the
+       lattice's dimension must be 0. */
+    double   body_accel[3];
+    /* > 0: interface width W = (rho_l - rho_v) / max |grad rho| (Sec. 3.1.1)
+       from which kappa_tilde is derived (elmrt_kappa_for_width); 0: use
+       kappa_tilde as given. */
+    double   target_W;
 } elmrt_params;
 
 /* Bytes of device workspace the problem needs (populations twice, density
@@ -89,7 +107,10 @@ elmrt_status elmrt_workspace_bytes(const elmrt_params* p, size_t* bytes);
  * precision, collision or bc; n < 4 on an axis (nz != 1 for D2Q9); cells
  * >= 2^31; Q x (cells per plane normal to the last axis) x value size
  * >= 2^31 bytes; a, b, R <= 0; T/Tc outside (0, 1); kappa_tilde < 0;
- * nu <= 0; rho_liquid <= rho_vapour when the viscosities differ. */
+ * nu <= 0; rho_liquid <= rho_vapour when the viscosities differ; unknown
+ * readings bits; a non-finite body acceleration, or one along an axis the
+ * lattice lacks; target_W < 0, or target_W > 0 with kappa_tilde != 0, or a
+ * temperature without a two-phase region when target_W > 0. */
 elmrt_status elmrt_create(const elmrt_params* p, void* dev_workspace, size_t workspace_bytes,
                           void* hip_stream, elmrt_sim** out);
 
@@ -192,6 +213,17 @@ int32_t elmrt_velocities(int32_t lattice, int32_t* c);
 elmrt_status elmrt_coexistence(const elmrt_params* p, double* rho_vapour, double* rho_liquid,
                                double* p_sat);
 
+/* Capillarity kappa~ for an interface of width W (> 0) of the EOS in p at its
+ * T/Tc, host FP64: the square-gradient first integral (kappa~/2) rho'^2 =
+ * omega(rho) of a flat interface, with the excess grand potential omega(rho)
+ * = rho int_{rho_v}^{rho} (P(s) - P_sat)/s^2 ds between the Maxwell densities
+ * (textbook van der Waals theory; the paper does not give kappa~), makes the
+ * steepest gradient sqrt(2 max omega / kappa~), so kappa~ = 2 max(omega) W^2
+ * / (rho_l - rho_v)^2.  The integral is the closed-form antiderivative of P/s^2.
+ * The model's converged interfaces approach W as W grows (at W = 5 they are
+ * some 30 % wider: the stencils' own discretisation). */
+elmrt_status elmrt_kappa_for_width(const elmrt_params* p, double W, double* kappa);
+
 /* Peng-Robinson pressure P(rho) (Sec. 3.1) of the EOS in p at its T/Tc, for
  * n host FP64 densities (post-processing: Laplace pressure jumps). */
 elmrt_status elmrt_pressure(const elmrt_params* p, const double* rho, double* P, int64_t n);
@@ -280,29 +312,32 @@ void elmrt_destroy(elmrt_sim* s);
  * elmrt_init_fields, a step count) are queued by elmrt_server_submit and
  * admitted in arrival order while their workspace fits a caller-owned device
  * pool (first fit; a job that does not fit waits, and so do the ones behind
- * it).  Admitted jobs stay resident and are advanced in rounds by
- * elmrt_server_run: in every round the resident jobs first in the scheduling
- * order (elmrt_server_set_policy: least remaining work, cells x steps, first
- * -- the default -- or arrival order), until their cells reach a fill budget
- * (elmrt_server_set_fill, default 2^22 cells, at least one job), form one
- * batch per lattice and precision (the elmrt_batch_* entry points) that
- * advances by chunk_steps, or by the fewest steps any of them still needs,
- * so every job stops exactly at its step count; small jobs share rounds,
- * large ones take turns.
- * A round first enqueues its steps on the compute stream (the caller's);
- * while the device works it reads out the jobs whose last steps were
- * enqueued in earlier rounds (fields and sums kept on the host until
- * elmrt_server_result), returns their memory to the pool, and uploads and
- * initialises newly admitted jobs, both on a second stream the server
- * creates (non-blocking, default priority); admitted jobs join the next
- * round.  After its steps in a round, each job's instability flag is copied
- * to pinned host memory (elmrt_poll_unstable); a job seen unstable is
+ * it).  Admitted jobs stay resident and are advanced in rounds enqueued by
+ * elmrt_server_run: a round takes the resident jobs first in the scheduling
+ * order (elmrt_server_set_policy: arrival order -- the default -- least
+ * remaining work -- cells x steps -- first, or that with the oldest job
+ * always first) until
+ * their cells reach a fill budget (elmrt_server_set_fill, default 2^22
+ * cells, at least one job), and advances them as one batch per lattice and
+ * precision (the elmrt_batch_* machinery, without graphs): the costliest
+ * batch by chunk_steps, a cheaper one by proportionally more steps (bytes
+ * per step: D2Q9 132 B, D3Q27 356 B per cell), none beyond the fewest steps a
+ * member still needs, so every job stops exactly at its step count.
+ * A scheduling pass (one per 'rounds' of elmrt_server_run) never waits for
+ * the device: it reads out the jobs whose last round has completed (fields
+ * and sums kept on the host until elmrt_server_result) and returns their
+ * memory to the pool, uploads and initialises newly admitted jobs -- both on
+ * a second stream the server creates (non-blocking, default priority) --
+ * and enqueues the next round on the compute stream (the caller's) while
+ * fewer than two rounds are in flight; a pass with nothing to do pauses for
+ * 0.1 ms.  After its steps in a round, each job's instability flag is
+ * copied to pinned host memory (elmrt_poll_unstable); a job seen unstable is
  * evicted: it is not advanced further, and is read out (status
  * ELMRT_E_UNSTABLE, fields as they stand) and its memory freed while the
- * others continue.  A job's result is bitwise the same as the same simulation run
- * alone.  The server owns its job records; the pool and the stream are the
- * caller's and must outlive it.  Not thread-safe: one thread drives a
- * server. */
+ * others continue.  A job's result is bitwise the same as the same
+ * simulation run alone.  The server owns its job records; the pool and the
+ * stream are the caller's and must outlive it.  Not thread-safe: one thread
+ * drives a server. */
 typedef struct elmrt_server elmrt_server;
 
 /* dev_pool: device memory (256-byte aligned, >= 4096 bytes) the server carves
@@ -315,9 +350,9 @@ elmrt_status elmrt_server_create(void* dev_pool, size_t pool_bytes, void* stream
 /* Cells a round advances at most (beyond the first job); >= 1. */
 elmrt_status elmrt_server_set_fill(elmrt_server* s, int64_t cells);
 
-/* Scheduling order of resident jobs: 0 arrival, 1 least remaining work
- * (cells x remaining steps) first, 2 as 1 but the oldest resident job always
- * first (it advances every round, so none starves). */
+/* Scheduling order of resident jobs: 0 arrival (the default), 1 least
+ * remaining work (cells x remaining steps) first, 2 as 1 but the oldest
+ * resident job always first (it advances every round, so none starves). */
 elmrt_status elmrt_server_set_policy(elmrt_server* s, int32_t policy);
 
 /* Queue a job; the fields (rho0[N], u0[D][N], FP64 host) are copied.  Fails
@@ -325,10 +360,11 @@ elmrt_status elmrt_server_set_policy(elmrt_server* s, int32_t policy);
 elmrt_status elmrt_server_submit(elmrt_server* s, const elmrt_params* p, const double* rho0, const double* u0,
                                  int64_t steps, int64_t* job_id);
 
-/* Run up to 'rounds' rounds (one batched advance per lattice and precision,
- * retirement of jobs finished earlier, admission); returns early when no job
- * is queued or resident.  *queued, *resident (may be NULL) count the jobs
- * waiting and on the device (including finished ones not yet read out). */
+/* Run up to 'rounds' scheduling passes (retirement of jobs whose last round
+ * has completed, admission, and a new round while fewer than two are in
+ * flight); returns early when no job is queued or resident.  *queued,
+ * *resident (may be NULL) count the jobs waiting and on the device (including
+ * finished ones not yet read out). */
 elmrt_status elmrt_server_run(elmrt_server* s, int32_t rounds, int32_t* queued, int32_t* resident);
 
 /* State of a job (0 queued, 1 resident, 2 done, 3 failed), its submit /

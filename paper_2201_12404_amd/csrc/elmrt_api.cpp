@@ -13,6 +13,7 @@
 #include <cstdio>
 #include <cstring>
 #include <string>
+#include <mutex>
 #include <vector>
 
 namespace {
@@ -176,8 +177,56 @@ elmrt_status validate(const elmrt_params* p)
     if (!(p->nu_liquid > 0) || !(p->nu_vapour > 0)) return fail(ELMRT_E_INVALID, "viscosities must be > 0");
     if (p->nu_liquid != p->nu_vapour && !(p->rho_liquid > p->rho_vapour && p->rho_vapour >= 0))
         return fail(ELMRT_E_INVALID, "rho_liquid must exceed rho_vapour when the viscosities differ");
-    if (p->reserved != 0) return fail(ELMRT_E_INVALID, "reserved must be 0");
+    if (p->readings & ~(ELMRT_READING_TRACE_IN_S | ELMRT_READING_PHI_FLUID_VELOCITY))
+        return fail(ELMRT_E_INVALID, "unknown readings bits");
+    for (int a = 0; a < 3; ++a) {
+        if (!std::isfinite(p->body_accel[a])) return fail(ELMRT_E_INVALID, "body_accel must be finite");
+        if (a >= D && p->body_accel[a] != 0.0) return fail(ELMRT_E_INVALID, "body_accel along an axis the lattice lacks");
+    }
+    if (!(p->target_W >= 0) || !std::isfinite(p->target_W)) return fail(ELMRT_E_INVALID, "target_W must be >= 0");
+    if (p->target_W > 0 && p->kappa_tilde != 0)
+        return fail(ELMRT_E_INVALID, "give kappa_tilde or target_W, not both");
     return ELMRT_OK;
+}
+
+// Square-gradient capillarity of an interface of width W: kappa~ = 2 max
+// omega W^2 / (rho_l - rho_v)^2, omega(rho) = rho [G(rho) - G(rho_v) + P_sat
+// (1/rho - 1/rho_v)] with G the antiderivative of P/rho^2.  omega vanishes at
+// both Maxwell densities and peaks where mu(rho) = mu_sat between the
+// spinodals: a scan, then golden-section refinement of the bracket.
+bool kappa_for_width(const PengRobinson& pr, double W, double* kappa)
+{
+    double rv, rl, ps;
+    if (!maxwell(pr, &rv, &rl, &ps)) return false;
+    const double Gv = pr.G(rv);
+    auto omega = [&](double r) { return r * (pr.G(r) - Gv + ps * (1.0 / r - 1.0 / rv)); };
+    const int NS = 4000;
+    int kbest = 1;
+    double best = -1.0;
+    for (int k = 1; k < NS; ++k) {
+        const double om = omega(rv + (rl - rv) * k / NS);
+        if (om > best) { best = om; kbest = k; }
+    }
+    double lo = rv + (rl - rv) * (kbest - 1) / NS, hi = rv + (rl - rv) * (kbest + 1) / NS;
+    const double g = 0.5 * (std::sqrt(5.0) - 1.0);
+    for (int it = 0; it < 200 && hi - lo > 1e-15 * rl; ++it) {
+        const double a = hi - g * (hi - lo), b = lo + g * (hi - lo);
+        (omega(a) > omega(b) ? hi : lo) = omega(a) > omega(b) ? b : a;
+    }
+    best = std::max(best, omega(0.5 * (lo + hi)));
+    *kappa = 2.0 * best * W * W / ((rl - rv) * (rl - rv));
+    return true;
+}
+
+// kappa~ of the problem: as given, or derived from target_W.
+bool problem_kappa(const elmrt_params* p, double* kappa)
+{
+    if (!(p->target_W > 0)) {
+        *kappa = p->kappa_tilde;
+        return true;
+    }
+    PengRobinson pr(p->eos_a, p->eos_b, p->eos_R, p->acentric, p->T_over_Tc);
+    return kappa_for_width(pr, p->target_W, kappa);
 }
 
 struct Layout {
@@ -290,7 +339,10 @@ elmrt_status elmrt_create(const elmrt_params* p, void* ws, size_t ws_bytes, void
     s->ph.RT = pr.RT;
     s->ph.b = pr.b;
     s->ph.aal = pr.aal;
-    s->ph.kappa = p->kappa_tilde;
+    if (!problem_kappa(p, &s->ph.kappa)) {
+        delete s;
+        return fail(ELMRT_E_INVALID, "target_W given at a temperature without a two-phase region");
+    }
     if (p->nu_liquid == p->nu_vapour) {
         s->ph.nu_v = p->nu_liquid;
         s->ph.dnu = 0.0;
@@ -303,6 +355,9 @@ elmrt_status elmrt_create(const elmrt_params* p, void* ws, size_t ws_bytes, void
         s->ph.inv_drho = 1.0 / (p->rho_liquid - p->rho_vapour);
     }
     s->ph.entropic = p->collision == ELMRT_ENTROPIC ? 1 : 0;
+    s->ph.trace_in_h = (p->readings & ELMRT_READING_TRACE_IN_S) ? 0 : 1;
+    s->ph.phi_fluid = (p->readings & ELMRT_READING_PHI_FLUID_VELOCITY) ? 1 : 0;
+    for (int a = 0; a < 3; ++a) s->ph.g[a] = p->body_accel[a];
     s->L.D = s->D;
     s->L.fp64 = p->precision == ELMRT_FP64;
     for (int a = 0; a < 3; ++a) {
@@ -389,8 +444,10 @@ static elmrt_status step_impl(elmrt_sim* s, int64_t nsteps, hipEvent_t* ev)
     for (int64_t k = 0; k < nsteps; ++k) {
         void* cur = s->buf[s->cur];
         void* nxt = s->buf[1 - s->cur];
-        e = elmrt::launch_macro(s->L, cur, s->rho, s->q, s->flag, 1.0 / s->ph.b);
+        e = elmrt::launch_macro(s->L, cur, s->rho, s->q, s->flag, 1.0 / s->ph.b, s->ph.phi_fluid);
         if (e != hipSuccess) return hip_fail(e, "moment kernel");
+        if (s->ph.phi_fluid && (e = elmrt::launch_flux_fluid(s->L, s->rho, s->q, s->ph)) != hipSuccess)
+            return hip_fail(e, "flux kernel");
         if (ev && (e = hipEventRecord(ev[2 * k + 1], s->stream)) != hipSuccess) return hip_fail(e, "hipEventRecord");
         e = elmrt::launch_collide(s->L, s->tx, s->ty, member_depth(s, cap), cur, nxt, s->rho, s->q, s->ph, s->flag);
         if (e != hipSuccess) return hip_fail(e, "collision kernel");
@@ -542,6 +599,17 @@ elmrt_status elmrt_coexistence(const elmrt_params* p, double* rho_vapour, double
     if (!(p->T_over_Tc > 0 && p->T_over_Tc < 1)) return fail(ELMRT_E_INVALID, "T/Tc must be in (0, 1)");
     PengRobinson pr(p->eos_a, p->eos_b, p->eos_R, p->acentric, p->T_over_Tc);
     if (!maxwell(pr, rho_vapour, rho_liquid, p_sat)) return fail(ELMRT_E_INVALID, "no two-phase region at this temperature");
+    return ELMRT_OK;
+}
+
+elmrt_status elmrt_kappa_for_width(const elmrt_params* p, double W, double* kappa)
+{
+    if (!p || !kappa) return fail(ELMRT_E_INVALID, "NULL argument");
+    if (!(W > 0) || !std::isfinite(W)) return fail(ELMRT_E_INVALID, "W must be > 0");
+    if (!(p->eos_a > 0) || !(p->eos_b > 0) || !(p->eos_R > 0)) return fail(ELMRT_E_INVALID, "EOS a, b, R must be > 0");
+    if (!(p->T_over_Tc > 0 && p->T_over_Tc < 1)) return fail(ELMRT_E_INVALID, "T/Tc must be in (0, 1)");
+    PengRobinson pr(p->eos_a, p->eos_b, p->eos_R, p->acentric, p->T_over_Tc);
+    if (!kappa_for_width(pr, W, kappa)) return fail(ELMRT_E_INVALID, "no two-phase region at this temperature");
     return ELMRT_OK;
 }
 
@@ -780,6 +848,9 @@ struct elmrt_batch {
     long long mblocks = 0;
     int parity = 0;                     // steps since the table was built, mod 2
     bool use_graph = true;
+    bool table_unused = false;          // no kernel has read djobs yet (the request
+                                        // loop's fresh tables): upload without
+                                        // waiting for the members' stream
     hipGraphExec_t exec = nullptr;      // two steps (parity 0 then 1)
     hipGraph_t graph = nullptr;
     hipStream_t capture = nullptr;      // private stream the graph is captured on
@@ -802,6 +873,25 @@ struct elmrt_batch {
 namespace {
 
 size_t batch_table_bytes(int count) { return align_up((size_t)count * sizeof(elmrt::BatchJob)); }
+
+elmrt_status batch_create_impl(elmrt_sim* const* sims, int32_t count, void* ws, size_t ws_bytes,
+                               elmrt_batch** out, bool fresh);
+
+// A non-blocking stream of the library's (one per device, created on first
+// use) for host-to-device copies that must not wait for compute streams.
+hipError_t upload_stream(hipStream_t* out)
+{
+    static std::mutex mu;
+    static hipStream_t streams[elmrt::kMaxDevices] = {};
+    int dev = 0;
+    hipError_t e = hipGetDevice(&dev);
+    if (e != hipSuccess) return e;
+    if (dev < 0 || dev >= elmrt::kMaxDevices) return hipErrorInvalidDevice;
+    std::lock_guard<std::mutex> lock(mu);
+    if (!streams[dev] && (e = hipStreamCreateWithFlags(&streams[dev], hipStreamNonBlocking)) != hipSuccess) return e;
+    *out = streams[dev];
+    return hipSuccess;
+}
 
 // (Re)build the device job table from the sims' current state and tilings.
 elmrt_status batch_build(elmrt_batch* b)
@@ -854,10 +944,20 @@ elmrt_status batch_build(elmrt_batch* b)
     b->mblocks = mfirst;
     b->parity = 0;
     b->drop_graph();
+    // A table that kernels enqueued earlier may still read is replaced only
+    // after the members' stream has drained; a table no kernel has read yet
+    // goes up on the library's own upload stream, without waiting for the
+    // compute already enqueued.
+    hipStream_t up = b->stream;
+    if (b->table_unused) {
+        hipError_t e = upload_stream(&up);
+        if (e != hipSuccess) return hip_fail(e, "upload stream");
+    }
     hipError_t e = hipMemcpyAsync(b->djobs, b->hjobs.data(), (size_t)n * sizeof(elmrt::BatchJob),
-                                  hipMemcpyHostToDevice, b->stream);
-    if (e == hipSuccess) e = hipStreamSynchronize(b->stream);
+                                  hipMemcpyHostToDevice, up);
+    if (e == hipSuccess) e = hipStreamSynchronize(up);
     if (e != hipSuccess) return hip_fail(e, "job table upload");
+    b->table_unused = false;
     return ELMRT_OK;
 }
 
@@ -868,6 +968,14 @@ elmrt_status batch_enqueue_step(elmrt_batch* b, int parity, hipStream_t stream)
     hipError_t e = elmrt::launch_macro_batch(b->D, b->fp64, b->djobs, (int)b->hjobs.size(), b->mblocks, parity,
                                              stream);
     if (e != hipSuccess) return hip_fail(e, "batched moment kernel");
+    // members whose Phi flux takes the fluid velocity: their flux pass, one
+    // launch each, once every density of the member is known
+    for (const elmrt_sim* s : b->sims) {
+        if (!s->ph.phi_fluid) continue;
+        elmrt::Launch L = s->L;
+        L.stream = stream;
+        if ((e = elmrt::launch_flux_fluid(L, s->rho, s->q, s->ph)) != hipSuccess) return hip_fail(e, "flux kernel");
+    }
     for (const auto& G : b->groups) {
         e = elmrt::launch_collide_batch(b->D, b->fp64, G.tx, G.ty, b->djobs + G.first, G.count, G.blocks, parity,
                                         stream);
@@ -957,8 +1065,31 @@ elmrt_status elmrt_batch_workspace_bytes(int32_t count, size_t* bytes)
     return ELMRT_OK;
 }
 
+}  // extern "C"
+
+// The request loop's batches: a workspace no kernel has touched yet (the loop
+// releases a table's memory only after the rounds that read it have
+// completed), so the table goes up without waiting for the compute stream;
+// and no graph, since such a batch lives for a few rounds.
+elmrt_status elmrt::batch_create_fresh(elmrt_sim* const* sims, int32_t count, void* ws, size_t ws_bytes,
+                                       elmrt_batch** out)
+{
+    return batch_create_impl(sims, count, ws, ws_bytes, out, true);
+}
+
+extern "C" {
+
 elmrt_status elmrt_batch_create(elmrt_sim* const* sims, int32_t count, void* ws, size_t ws_bytes,
                                 elmrt_batch** out)
+{
+    return batch_create_impl(sims, count, ws, ws_bytes, out, false);
+}
+
+}  // extern "C"
+
+namespace {
+elmrt_status batch_create_impl(elmrt_sim* const* sims, int32_t count, void* ws, size_t ws_bytes,
+                               elmrt_batch** out, bool fresh)
 {
     if (!out) return fail(ELMRT_E_INVALID, "out is NULL");
     *out = nullptr;
@@ -982,6 +1113,8 @@ elmrt_status elmrt_batch_create(elmrt_sim* const* sims, int32_t count, void* ws,
     b->fp64 = v[0]->L.fp64;
     b->stream = v[0]->stream;
     b->djobs = (elmrt::BatchJob*)ws;
+    b->table_unused = fresh;
+    b->use_graph = !fresh;
     elmrt_status st = batch_build(b);
     if (st != ELMRT_OK) {
         delete b;
@@ -990,6 +1123,9 @@ elmrt_status elmrt_batch_create(elmrt_sim* const* sims, int32_t count, void* ws,
     *out = b;
     return ELMRT_OK;
 }
+}  // namespace
+
+extern "C" {
 
 elmrt_status elmrt_batch_step(elmrt_batch* b, int64_t nsteps)
 {

@@ -4,6 +4,8 @@
 
 #include <hip/hip_runtime.h>
 
+#include "../../include/elmrt.h"
+
 #include <string>
 #include <stdint.h>
 
@@ -36,7 +38,10 @@ struct Phys {
     T dnu;         // nu_l - nu_v
     T rho_v;       // lower density anchor of nu(rho)
     T inv_drho;    // 1 / (rho_l - rho_v), 0 when nu is uniform
+    T g[3];        // uniform body acceleration (F gains rho g)
     int entropic;  // 1: entropic gamma, 0: BGK
+    int trace_in_h;  // 1: the trace of the second moments is part of h, 0: of s
+    int phi_fluid;   // 1: the flux of Phi uses the fluid velocity u + F/(2 rho)
 };
 
 // One simulation of a batch: its buffers, grid, constants and tilings, and the
@@ -67,7 +72,13 @@ struct Launch {
 
 // The instability flag is raised for a non-finite or non-positive density, or
 // one at or beyond rho_max = 1/b, the pole of the Peng-Robinson pressure.
-hipError_t launch_macro(const Launch& L, const void* cur, void* rho, void* q, unsigned* flag, double rho_max);
+// q_momentum: store rho u in q (for launch_flux_fluid) instead of the flux.
+hipError_t launch_macro(const Launch& L, const void* cur, void* rho, void* q, unsigned* flag, double rho_max,
+                        int q_momentum);
+
+// q := rho v^3 per component, v = (q + F/2) / rho with F the force on the
+// density field: the flux of Phi with the fluid velocity (q holds rho u).
+hipError_t launch_flux_fluid(const Launch& L, const void* rho, void* q, const Phys<double>& ph);
 
 hipError_t launch_collide(const Launch& L, int tx, int ty, int tm, const void* cur, void* nxt,
                           const void* rho, const void* q, const Phys<double>& ph, unsigned* flag);
@@ -128,5 +139,11 @@ hipError_t launch_macro_batch(int D, int fp64, const BatchJob* jobs, int njobs, 
                               hipStream_t stream);
 hipError_t launch_collide_batch(int D, int fp64, int tx, int ty, const BatchJob* jobs, int njobs,
                                 long long blocks, int parity, hipStream_t stream);
+
+// elmrt_batch_create for a workspace that no kernel has read yet: the job
+// table is uploaded without waiting for the members' stream, and the batch
+// enqueues its launches directly (no graph).  Used by the request loop.
+elmrt_status batch_create_fresh(elmrt_sim* const* sims, int32_t count, void* ws, size_t ws_bytes,
+                                elmrt_batch** out);
 
 }  // namespace elmrt

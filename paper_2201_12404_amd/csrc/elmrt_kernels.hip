@@ -321,7 +321,7 @@ __device__ __forceinline__ void conserve_mass(T (&f)[Lat<D>::Q], A rho)
 // dual functions of the x and y axes.
 template <int D, typename T, typename A>
 __device__ __forceinline__ bool collide(T (&f)[Lat<D>::Q], A rho, const A (&j)[3], const A (&F)[3],
-                                        const A (&Phi)[3], A omega, int entropic)
+                                        const A (&Phi)[3], A omega, int entropic, int trace_in_h)
 {
     constexpr int Q = Lat<D>::Q;
     constexpr int ZL = (D == 3) ? 0 : 1, ZH = (D == 3) ? 2 : 1;   // z index range (c_z + 1)
@@ -418,8 +418,9 @@ __device__ __forceinline__ bool collide(T (&f)[Lat<D>::Q], A rho, const A (&j)[3
         if constexpr (sizeof(T) < sizeof(A)) conserve_mass<D, T, A>(f, rho);
         return false;
     }
-    // trace in h: s carries the deviatoric part only
-    {
+    // trace in h (the default reading): s carries the deviatoric part only;
+    // otherwise s takes the whole second-order block
+    if (trace_in_h) {
         const T tr = (D == 3) ? (Pxx + Pyy + Pzz) * (T(1) / T(3)) : (Pxx + Pyy) * T(0.5);
         Pxx -= tr;
         Pyy -= tr;
@@ -752,7 +753,7 @@ __device__ __forceinline__ TileCoords tile_of(const Grid& g, int b, int bx, int 
 template <int D, typename T, int TX, int TY>
 __device__ __forceinline__ void macro_tile(int b, const T* __restrict__ cur, T* __restrict__ rho_out,
                                            T* __restrict__ q_out, unsigned* __restrict__ flag, const Grid& g,
-                                           int bx, int by, int tm, double rho_max)
+                                           int bx, int by, int tm, double rho_max, int q_momentum)
 {
     constexpr int Q = Lat<D>::Q;
     // top-down: the planes read last are the bottom ones, which the collision
@@ -783,8 +784,10 @@ __device__ __forceinline__ void macro_tile(int b, const T* __restrict__ cur, T* 
         const double inv = rcp<double>(rho);
 #pragma unroll
         for (int a = 0; a < D; ++a) {
+            // q_momentum: rho u_a, for k_flux_fluid to turn into q once the
+            // density field, and with it the force, is complete
             const double ua = j[a] * inv;
-            pst<T, true>(plane_ptr(q_out + (size_t)a * g.N + mself), L.ip, (T)(j[a] * ua * ua));
+            pst<T, true>(plane_ptr(q_out + (size_t)a * g.N + mself), L.ip, (T)(q_momentum ? j[a] : j[a] * ua * ua));
         }
         bad = bad || !(rho > 0.0) || !isfinite(rho) || rho >= rho_max;
     }
@@ -1004,10 +1007,10 @@ __device__ __forceinline__ void collide_tile(int b, const T* __restrict__ cur, T
             const double cg = c0psi * (wl / 3.0), ck = ph.kappa * wl * rhoc;
 #pragma unroll
             for (int a = 0; a < D; ++a) {
-                F[a] = cg * G[a] + ck * K[a];
+                F[a] = cg * G[a] + ck * K[a] + rhoc * ph.g[a];
                 Phi[a] = half_rate * dq[a];
             }
-            const bool fell_back = collide<D, T, double>(f, rhoc, j, F, Phi, omega, ph.entropic);
+            const bool fell_back = collide<D, T, double>(f, rhoc, j, F, Phi, omega, ph.entropic, ph.trace_in_h);
             // count the cells whose gamma fell back: one atomic per wavefront
             // and plane, only when some lane did
             const unsigned long long fb = __ballot(fell_back);
@@ -1045,9 +1048,9 @@ __device__ __forceinline__ int row_xcd_order(int b, int nb, int bx)
 template <int D, typename T, int TX, int TY>
 __global__ __launch_bounds__(TX* TY) void k_macro(const T* __restrict__ cur, T* __restrict__ rho_out,
                                                   T* __restrict__ q_out, unsigned* __restrict__ flag, Grid g,
-                                                  int bx, int by, int tm, double rho_max)
+                                                  int bx, int by, int tm, double rho_max, int q_momentum)
 {
-    macro_tile<D, T, TX, TY>((int)blockIdx.x, cur, rho_out, q_out, flag, g, bx, by, tm, rho_max);
+    macro_tile<D, T, TX, TY>((int)blockIdx.x, cur, rho_out, q_out, flag, g, bx, by, tm, rho_max, q_momentum);
 }
 
 template <int D, typename T, int TX, int TY>
@@ -1081,7 +1084,7 @@ __global__ __launch_bounds__(TX* TY) void k_macro_batch(const BatchJob* __restri
     const int j = job_of(jobs, njobs, b, &BatchJob::mfirst);
     const BatchJob& J = jobs[j];
     macro_tile<D, T, TX, TY>(b - J.mfirst, (const T*)J.buf[J.cur0 ^ parity], (T*)J.rho, (T*)J.q, J.flag, J.g,
-                             J.mbx, J.mby, J.mtm, 1.0 / J.ph.b);
+                             J.mbx, J.mby, J.mtm, 1.0 / J.ph.b, J.ph.phi_fluid);
 }
 
 template <int D, typename T, int TX, int TY>
@@ -1099,21 +1102,14 @@ __global__ __launch_bounds__(TX* TY) __attribute__((amdgpu_waves_per_eu(CollideW
                                gamma_fallbacks(J.flag));
 }
 
-// Velocity shift between the bare velocity u = sum c f / rho and the fluid
-// velocity u + F dt/(2 rho) of the exact-difference forcing: u += sign F/(2 rho)
-// in place, F the force of Sec. 2.3 on the density field (FP64, neighbours
-// fetched from global memory).  sign = -1 turns a prescribed initial fluid
-// velocity into the bare velocity of f^eq; sign = +1 turns a read-out bare
-// velocity into the fluid velocity.  rho is only read.
+// Force of Sec. 2.3 (psi and capillary stencils, reading R2, R3) plus the
+// body force rho g at cell co, in FP64, neighbours fetched from the density
+// field in global memory (ghosts mirrored about wall planes, reading R15).
 template <int D, typename T>
-__global__ __launch_bounds__(256) void k_shift_velocity(const T* __restrict__ rho, T* __restrict__ u, Grid g,
-                                                        FlatGrid fg, Phys<double> ph, double sign)
+__device__ __forceinline__ double force_at(const T* __restrict__ rho, const Grid& g, const int (&co)[3],
+                                          const Phys<double>& ph, double (&F)[3])
 {
     constexpr int Q = Lat<D>::Q;
-    const uint32_t cell = blockIdx.x * 256u + threadIdx.x;
-    if (cell >= (uint32_t)g.N) return;
-    int co[3];
-    flat_coords(cell, fg, co[0], co[1], co[2]);
     auto rho_at = [&](int dx, int dy, int dz) -> double {
         int flip = 0;
         const int x = map_coord(co[0] + dx, g.n[0], g.wall[0], &flip);
@@ -1121,7 +1117,7 @@ __global__ __launch_bounds__(256) void k_shift_velocity(const T* __restrict__ rh
         const int z = (D == 3) ? map_coord(co[2] + dz, g.n[2], g.wall[2], &flip) : 0;
         return (double)rho[x + g.n[0] * y + g.nxny * z];
     };
-    const double r0 = (double)rho[cell];
+    const double r0 = rho_at(0, 0, 0);
     const double psi0 = psi_signed<double>(r0, ph);
     double G[3] = {0.0, 0.0, 0.0}, K[3] = {0.0, 0.0, 0.0};
 #pragma unroll
@@ -1142,11 +1138,51 @@ __global__ __launch_bounds__(256) void k_shift_velocity(const T* __restrict__ rh
             if (c[a] < 0) { G[a] -= tt; K[a] -= kk; }
         }
     }
+    for (int a = 0; a < 3; ++a) F[a] = (a < D) ? 2.0 * psi0 * G[a] + ph.kappa * r0 * K[a] + r0 * ph.g[a] : 0.0;
+    return r0;
+}
+
+// Velocity shift between the bare velocity u = sum c f / rho and the fluid
+// velocity u + F dt/(2 rho) of the exact-difference forcing: u += sign F/(2 rho)
+// in place, F the force on the density field (force_at).  sign = -1 turns a
+// prescribed initial fluid velocity into the bare velocity of f^eq; sign = +1
+// turns a read-out bare velocity into the fluid velocity.  rho is only read.
+template <int D, typename T>
+__global__ __launch_bounds__(256) void k_shift_velocity(const T* __restrict__ rho, T* __restrict__ u, Grid g,
+                                                        FlatGrid fg, Phys<double> ph, double sign)
+{
+    const uint32_t cell = blockIdx.x * 256u + threadIdx.x;
+    if (cell >= (uint32_t)g.N) return;
+    int co[3];
+    flat_coords(cell, fg, co[0], co[1], co[2]);
+    double F[3];
+    const double r0 = force_at<D, T>(rho, g, co, ph, F);
 #pragma unroll
     for (int a = 0; a < D; ++a) {
-        const double F = 2.0 * psi0 * G[a] + ph.kappa * r0 * K[a];
         T& ua = u[(size_t)a * g.N + cell];
-        ua = (T)((double)ua + sign * F / (2.0 * r0));
+        ua = (T)((double)ua + sign * F[a] / (2.0 * r0));
+    }
+}
+
+// The flux of Phi with the fluid velocity (reading switch
+// ELMRT_READING_PHI_FLUID_VELOCITY): q holds rho u_a from the moment pass and
+// becomes q_a = rho v_a^3 with v = u + F/(2 rho), F on the complete density
+// field.  In place: cell r reads and writes only its own q.
+template <int D, typename T>
+__global__ __launch_bounds__(256) void k_flux_fluid(const T* __restrict__ rho, T* __restrict__ q, Grid g,
+                                                    FlatGrid fg, Phys<double> ph)
+{
+    const uint32_t cell = blockIdx.x * 256u + threadIdx.x;
+    if (cell >= (uint32_t)g.N) return;
+    int co[3];
+    flat_coords(cell, fg, co[0], co[1], co[2]);
+    double F[3];
+    const double r0 = force_at<D, T>(rho, g, co, ph, F);
+#pragma unroll
+    for (int a = 0; a < D; ++a) {
+        T& qa = q[(size_t)a * g.N + cell];
+        const double v = ((double)qa + 0.5 * F[a]) / r0;
+        qa = (T)(r0 * v * v * v);
     }
 }
 
@@ -1386,12 +1422,13 @@ hipError_t collide_batch_dispatch(int tx, int ty, const BatchJob* jobs, int njob
 }
 
 template <int D, typename T>
-hipError_t macro_t(const Launch& L, const void* cur, void* rho, void* q, unsigned* flag, double rho_max)
+hipError_t macro_t(const Launch& L, const void* cur, void* rho, void* q, unsigned* flag, double rho_max,
+                   int q_momentum)
 {
     const Tiling t = macro_tiling(D, L.g);
     if (t.blocks <= 0 || t.blocks > 0x7fffffffLL) return hipErrorInvalidConfiguration;
     hipLaunchKernelGGL((k_macro<D, T, kMacroTX, 1>), dim3((unsigned)t.blocks), dim3(kMacroTX, 1), 0, L.stream,
-                       (const T*)cur, (T*)rho, (T*)q, flag, L.g, t.bx, t.by, t.tm, rho_max);
+                       (const T*)cur, (T*)rho, (T*)q, flag, L.g, t.bx, t.by, t.tm, rho_max, q_momentum);
     return hipGetLastError();
 }
 
@@ -1477,12 +1514,28 @@ Tiling collide_tiling(int D, const Grid& g, int tx, int ty, int tm)
     return t;
 }
 
-hipError_t launch_macro(const Launch& L, const void* cur, void* rho, void* q, unsigned* flag, double rho_max)
+hipError_t launch_macro(const Launch& L, const void* cur, void* rho, void* q, unsigned* flag, double rho_max,
+                        int q_momentum)
 {
-    if (L.D == 2 && !L.fp64) return macro_t<2, float>(L, cur, rho, q, flag, rho_max);
-    if (L.D == 2) return macro_t<2, double>(L, cur, rho, q, flag, rho_max);
-    if (!L.fp64) return macro_t<3, float>(L, cur, rho, q, flag, rho_max);
-    return macro_t<3, double>(L, cur, rho, q, flag, rho_max);
+    if (L.D == 2 && !L.fp64) return macro_t<2, float>(L, cur, rho, q, flag, rho_max, q_momentum);
+    if (L.D == 2) return macro_t<2, double>(L, cur, rho, q, flag, rho_max, q_momentum);
+    if (!L.fp64) return macro_t<3, float>(L, cur, rho, q, flag, rho_max, q_momentum);
+    return macro_t<3, double>(L, cur, rho, q, flag, rho_max, q_momentum);
+}
+
+hipError_t launch_flux_fluid(const Launch& L, const void* rho, void* q, const Phys<double>& ph)
+{
+    const FlatGrid fg = flat_of(L.g);
+    const dim3 grid(flat_blocks(L.g)), block(256);
+    if (L.D == 2 && !L.fp64)
+        hipLaunchKernelGGL((k_flux_fluid<2, float>), grid, block, 0, L.stream, (const float*)rho, (float*)q, L.g, fg, ph);
+    else if (L.D == 2)
+        hipLaunchKernelGGL((k_flux_fluid<2, double>), grid, block, 0, L.stream, (const double*)rho, (double*)q, L.g, fg, ph);
+    else if (!L.fp64)
+        hipLaunchKernelGGL((k_flux_fluid<3, float>), grid, block, 0, L.stream, (const float*)rho, (float*)q, L.g, fg, ph);
+    else
+        hipLaunchKernelGGL((k_flux_fluid<3, double>), grid, block, 0, L.stream, (const double*)rho, (double*)q, L.g, fg, ph);
+    return hipGetLastError();
 }
 
 hipError_t launch_collide(const Launch& L, int tx, int ty, int tm, const void* cur, void* nxt,

@@ -7,11 +7,13 @@
 // precision (elmrt_batch_*) that advances by the chunk or by the fewest steps
 // any member still needs, so that jobs finish exactly; a job whose
 // instability flag is seen set (polled after every round without waiting) is
-// evicted and read out early.  Host transfers overlap
-// the device work: a round first enqueues its steps on the compute stream,
-// then reads out the jobs that finished in earlier rounds and uploads newly
-// admitted ones on a second stream of the server's own; finished jobs' memory
-// returns to the pool once read out.  Built on the public entry points only.
+// evicted and read out early.  A scheduling pass never waits for the device:
+// it reads out the jobs whose last round has completed and uploads newly
+// admitted ones on a second stream of the server's own, and enqueues the
+// next round on the compute stream while fewer than two are in flight;
+// finished jobs' memory returns to the pool once read out.  Built on the
+// public entry points, and on the library's batch construction for tables
+// that no kernel has read yet.
 #include "../../include/elmrt.h"
 #include "elmrt_internal.h"
 
@@ -24,6 +26,7 @@
 #include <map>
 #include <memory>
 #include <string>
+#include <thread>
 #include <vector>
 
 namespace {
@@ -117,6 +120,12 @@ struct Group {                          // resident jobs of one (lattice, precis
     std::vector<Job*> members;
     size_t off = 0;
     bool has_table = false;
+    int64_t used_round = -1;            // last round that enqueued this batch's steps
+};
+
+struct RetiredTable {                   // pool memory of a replaced batch's job table
+    size_t off;
+    int64_t round;                      // free once this round's compute has completed
 };
 
 }  // namespace
@@ -135,13 +144,15 @@ struct elmrt_server {
     std::vector<int> free_slots;
     int64_t chunk = 100;
     int64_t fill = 4 << 20;             // cells advanced per round (at least one job)
-    int32_t policy = 1;                 // 0 arrival order, 1 shortest remaining work first,
+    int32_t policy = 0;                 // 0 arrival order, 1 shortest remaining work first,
                                         // 2 as 1 with the oldest job in every round
     int64_t next_id = 1;
     std::deque<Job*> queue;
     std::vector<Job*> resident;
     std::map<int64_t, std::unique_ptr<Job>> jobs;
     Group groups[4];                    // index 2 * lattice + precision
+    std::vector<RetiredTable> retired;
+    int64_t done_round = -1;            // every round <= this one has completed on the device
     int64_t lattice_updates = 0;        // cells x steps advanced
 
     ~elmrt_server()
@@ -218,14 +229,34 @@ elmrt_status retire(elmrt_server* s, Job* j)
     return ELMRT_OK;
 }
 
-// Make group g's batch match its members (rebuilt when the set changed).
+// Return to the pool the tables of replaced batches whose last round has
+// completed on the device.
+void release_retired(elmrt_server* s)
+{
+    std::vector<RetiredTable> keep;
+    for (const RetiredTable& t : s->retired) {
+        if (t.round <= s->done_round) s->pool->release(t.off);
+        else keep.push_back(t);
+    }
+    s->retired.swap(keep);
+}
+
+// Make group g's batch match its members (rebuilt when the set changed).  The
+// old batch is released at once (it owns no device memory); its table's pool
+// memory only after the last round that read it has completed, so the new
+// table never lands on memory a kernel may still read, and the host need not
+// wait for the device here.
 elmrt_status sync_batch(elmrt_server* s, Group& g, const std::vector<Job*>& members)
 {
     if (g.batch && members == g.members) return ELMRT_OK;
     if (g.batch) elmrt_batch_destroy(g.batch);
     g.batch = nullptr;
-    if (g.has_table) s->pool->release(g.off);
+    if (g.has_table) {
+        if (g.used_round < 0 || g.used_round <= s->done_round) s->pool->release(g.off);
+        else s->retired.push_back({g.off, g.used_round});
+    }
     g.has_table = false;
+    g.used_round = -1;
     g.members = members;
     if (members.empty()) return ELMRT_OK;
     size_t bytes = 0;
@@ -235,28 +266,75 @@ elmrt_status sync_batch(elmrt_server* s, Group& g, const std::vector<Job*>& memb
     g.has_table = true;
     std::vector<elmrt_sim*> sims;
     for (Job* j : members) sims.push_back(j->sim);
-    return elmrt_batch_create(sims.data(), (int32_t)sims.size(), s->pool_base + g.off, bytes, &g.batch);
+    return elmrt::batch_create_fresh(sims.data(), (int32_t)sims.size(), s->pool_base + g.off, bytes, &g.batch);
 }
 
-// Wait until the compute enqueued by the previous rounds is complete.
-elmrt_status wait_compute(elmrt_server* s, int slot)
+// Wait until the compute enqueued by the rounds up to 'round' (whose event
+// sits in 'slot') is complete.
+elmrt_status wait_compute(elmrt_server* s, int slot, int64_t round)
 {
     if (!s->ev_recorded[slot]) return ELMRT_OK;
     const hipError_t e = hipEventSynchronize(s->ev[slot]);
     if (e != hipSuccess) return sfail(ELMRT_E_DEVICE, std::string("hipEventSynchronize: ") + hipGetErrorString(e));
+    s->done_round = std::max(s->done_round, round);
     return ELMRT_OK;
 }
 
-elmrt_status round_once(elmrt_server* s)
+// Rounds known complete: the in-flight rounds' events, queried in order
+// (no wait).  At most two rounds are in flight, so the two event slots (by
+// round parity) are reused only once their round has completed.
+void poll_done(elmrt_server* s)
 {
-    const int cur = (int)(s->round & 1), prev = cur ^ 1;
-    // This round advances resident jobs with steps left, in policy order
-    // (arrival, or least remaining work -- cells x steps -- first), until their
-    // cells reach the fill budget: enough work to occupy the device, while the
-    // others wait their turn instead of slowing every running one down.
-    // a job whose flag was seen set is evicted: it is not advanced further
+    for (int64_t r = s->done_round + 1; r < s->round; ++r) {
+        const int slot = (int)(r & 1);
+        if (!s->ev_recorded[slot] || hipEventQuery(s->ev[slot]) != hipSuccess) break;
+        s->done_round = r;
+    }
+}
+
+// Relative device cost of one step of a cell: bytes per lattice update of
+// the two-pass step (D2Q9 132 B, D3Q27 356 B).
+double cell_cost(int D) { return D == 3 ? 356.0 / 132.0 : 1.0; }
+
+// One scheduling pass, which never waits for the device: retire the jobs
+// whose last round has completed (read-out on the io stream), admit queued
+// jobs that fit the pool (upload and initialisation on the io stream), and,
+// while fewer than two rounds are in flight, enqueue the next round on the
+// compute stream.  A round advances resident jobs with steps left, in
+// policy order (arrival, or least remaining work -- cells x steps -- first),
+// until their cells reach the fill budget: enough work to occupy the device,
+// while the others wait their turn instead of slowing every running one down.
+// Each (lattice, precision) group of the round is one batch; the costliest
+// group advances by the chunk, a cheaper one by proportionally more steps (so
+// that a small job beside a large one is not held to the large one's pace),
+// and no group beyond the fewest steps any of its members still needs, so
+// that every job stops exactly at its step count.  A job whose polled flag
+// is seen set is evicted: not advanced further, read out as it stands.
+elmrt_status round_once(elmrt_server* s, bool* progressed)
+{
+    *progressed = false;
+    poll_done(s);
+    release_retired(s);
+    elmrt_status st;
     for (Job* j : s->resident)
         if (j->slot >= 0 && *(volatile uint32_t*)&s->flags[j->slot] != 0u) j->unstable = true;
+    // retire the finished jobs whose last steps have completed
+    std::vector<Job*> keep;
+    for (Job* j : s->resident) {
+        const bool finished = (j->done >= j->steps || j->unstable) && j->last_round <= s->done_round;
+        if (!finished) {
+            keep.push_back(j);
+            continue;
+        }
+        if ((st = retire(s, j)) != ELMRT_OK) return st;
+        *progressed = true;
+    }
+    s->resident.swap(keep);
+    // admit the queued jobs that now fit
+    const size_t before = s->queue.size();
+    if ((st = admit(s)) != ELMRT_OK) return st;
+    if (s->queue.size() != before) *progressed = true;
+    if (s->round - 1 - s->done_round >= 2) return ELMRT_OK;   // the device is two rounds ahead
     std::vector<Job*> order;
     for (Job* j : s->resident)
         if (j->done < j->steps && !j->unstable) order.push_back(j);
@@ -278,46 +356,44 @@ elmrt_status round_once(elmrt_server* s)
         running.push_back(j);
         cells += (int64_t)j->N;
     }
-    elmrt_status st;
-    for (int gi = 0; gi < 4; ++gi) {
-        std::vector<Job*> members;
-        for (Job* j : running)
-            if (2 * j->p.lattice + j->p.precision == gi) members.push_back(j);
-        Group& g = s->groups[gi];
-        if (g.batch && members != g.members && (st = wait_compute(s, prev)) != ELMRT_OK) return st;
-        st = sync_batch(s, g, members);
-        if (st != ELMRT_OK) return st;
-        if (members.empty()) continue;
-        int64_t n = s->chunk;
-        for (Job* j : members) n = std::min(n, j->steps - j->done);
-        st = elmrt_batch_step(g.batch, n);
-        if (st != ELMRT_OK) return st;
-        for (Job* j : members) {
-            j->done += n;
-            j->last_round = s->round;
-            s->lattice_updates += (int64_t)j->N * n;
-            if (j->slot >= 0 && (st = elmrt_poll_unstable(j->sim, &s->flags[j->slot])) != ELMRT_OK) return st;
+    const int cur = (int)(s->round & 1);
+    if (!running.empty()) {
+        std::vector<Job*> members[4];
+        double cost[4] = {0, 0, 0, 0}, top = 0;
+        for (Job* j : running) {
+            const int gi = 2 * j->p.lattice + j->p.precision;
+            members[gi].push_back(j);
+            cost[gi] += (double)j->N * cell_cost(j->D);
         }
+        for (double c : cost) top = std::max(top, c);
+        for (int gi = 0; gi < 4; ++gi) {
+            Group& g = s->groups[gi];
+            if ((st = sync_batch(s, g, members[gi])) != ELMRT_OK) return st;
+            if (members[gi].empty()) continue;
+            const double ratio = std::floor(top / cost[gi]);
+            int64_t n = s->chunk * (int64_t)std::min(ratio, 1e6);
+            for (Job* j : members[gi]) n = std::min(n, j->steps - j->done);
+            if ((st = elmrt_batch_step(g.batch, n)) != ELMRT_OK) return st;
+            g.used_round = s->round;
+            for (Job* j : members[gi]) {
+                j->done += n;
+                j->last_round = s->round;
+                s->lattice_updates += (int64_t)j->N * n;
+                if (j->slot >= 0 && (st = elmrt_poll_unstable(j->sim, &s->flags[j->slot])) != ELMRT_OK) return st;
+            }
+        }
+        hipError_t e = hipEventRecord(s->ev[cur], s->stream);
+        if (e != hipSuccess) return sfail(ELMRT_E_DEVICE, std::string("hipEventRecord: ") + hipGetErrorString(e));
+        s->ev_recorded[cur] = true;
+        ++s->round;
+        *progressed = true;
     }
-    hipError_t e = hipEventRecord(s->ev[cur], s->stream);
-    if (e != hipSuccess) return sfail(ELMRT_E_DEVICE, std::string("hipEventRecord: ") + hipGetErrorString(e));
-    s->ev_recorded[cur] = true;
-    // while the device works on this round: read out the jobs whose last
-    // steps were enqueued by an earlier round ...
-    std::vector<Job*> keep, finished;
-    for (Job* j : s->resident)
-        ((j->done >= j->steps || j->unstable) && j->last_round < s->round ? finished : keep).push_back(j);
-    if (!finished.empty() && (st = wait_compute(s, prev)) != ELMRT_OK) return st;
-    for (Job* j : finished)
-        if ((st = retire(s, j)) != ELMRT_OK) return st;
-    s->resident.swap(keep);
-    // ... and upload the jobs that now fit
-    if ((st = admit(s)) != ELMRT_OK) return st;
-    ++s->round;
-    if (s->resident.empty()) {   // release the last batches and their tables
-        if ((st = wait_compute(s, cur)) != ELMRT_OK) return st;
+    if (s->resident.empty() && s->queue.empty()) {   // idle: release the batches and their tables
+        for (int64_t r = s->done_round + 1; r < s->round; ++r)
+            if ((st = wait_compute(s, (int)(r & 1), r)) != ELMRT_OK) return st;
         for (auto& g : s->groups)
             if ((st = sync_batch(s, g, {})) != ELMRT_OK) return st;
+        release_retired(s);
     }
     return ELMRT_OK;
 }
@@ -398,8 +474,12 @@ elmrt_status elmrt_server_run(elmrt_server* s, int32_t rounds, int32_t* queued, 
     if (!s) return sfail(ELMRT_E_INVALID, "server is NULL");
     for (int32_t r = 0; r < rounds; ++r) {
         if (s->queue.empty() && s->resident.empty()) break;
-        elmrt_status st = round_once(s);
+        bool progressed = false;
+        elmrt_status st = round_once(s, &progressed);
         if (st != ELMRT_OK) return st;
+        // nothing to do until the device finishes a round: pause briefly
+        // rather than spin
+        if (!progressed) std::this_thread::sleep_for(std::chrono::microseconds(100));
     }
     if (queued) *queued = (int32_t)s->queue.size();
     if (resident) *resident = (int32_t)s->resident.size();

@@ -20,6 +20,7 @@ ELMRT_D2Q9, ELMRT_D3Q27 = 0, 1
 ELMRT_FP32, ELMRT_FP64 = 0, 1
 ELMRT_ENTROPIC, ELMRT_BGK = 0, 1
 ELMRT_PERIODIC, ELMRT_WALL = 0, 1
+ELMRT_READING_TRACE_IN_S, ELMRT_READING_PHI_FLUID_VELOCITY = 1, 2
 
 
 class ElmrtError(RuntimeError):
@@ -41,12 +42,14 @@ class elmrt_params(ctypes.Structure):
         ("collision", ctypes.c_int32),
         ("n", ctypes.c_int64 * 3),
         ("bc", ctypes.c_int32 * 3),
-        ("reserved", ctypes.c_int32),
+        ("readings", ctypes.c_int32),
         ("eos_a", ctypes.c_double), ("eos_b", ctypes.c_double), ("eos_R", ctypes.c_double),
         ("acentric", ctypes.c_double), ("T_over_Tc", ctypes.c_double),
         ("kappa_tilde", ctypes.c_double),
         ("nu_liquid", ctypes.c_double), ("nu_vapour", ctypes.c_double),
         ("rho_liquid", ctypes.c_double), ("rho_vapour", ctypes.c_double),
+        ("body_accel", ctypes.c_double * 3),
+        ("target_W", ctypes.c_double),
     ]
 
 
@@ -66,6 +69,7 @@ _SIGS = {
     "elmrt_velocities": (ctypes.c_int32, [ctypes.c_int32, ctypes.POINTER(ctypes.c_int32)]),
     "elmrt_coexistence": (ctypes.c_int, [ctypes.POINTER(elmrt_params), _dp, _dp, _dp]),
     "elmrt_pressure": (ctypes.c_int, [ctypes.POINTER(elmrt_params), _dp, _dp, ctypes.c_int64]),
+    "elmrt_kappa_for_width": (ctypes.c_int, [ctypes.POINTER(elmrt_params), ctypes.c_double, _dp]),
     "elmrt_set_tiling": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_int32, ctypes.c_int32, ctypes.c_int32]),
     "elmrt_set_stream": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p]),
     "elmrt_get_tiling": (ctypes.c_int, [ctypes.c_void_p, ctypes.POINTER(ctypes.c_int32),
@@ -147,6 +151,10 @@ class Params:
     nu_vapour: float = 0.02
     rho_liquid: float = 0.0
     rho_vapour: float = 0.0
+    body_accel: tuple = (0.0, 0.0, 0.0)
+    target_W: float = 0.0
+    trace_in_h: bool = True      # reading R6 (False: ELMRT_READING_TRACE_IN_S)
+    phi_velocity: int = 0        # reading R4 (1: ELMRT_READING_PHI_FLUID_VELOCITY)
 
     @property
     def D(self) -> int:
@@ -170,12 +178,17 @@ class Params:
         for k in range(3):
             p.n[k] = int(n[k])
             p.bc[k] = int(bc[k])
-        p.reserved = 0
+        p.readings = (0 if self.trace_in_h else ELMRT_READING_TRACE_IN_S) | \
+            (ELMRT_READING_PHI_FLUID_VELOCITY if self.phi_velocity else 0)
         p.eos_a, p.eos_b, p.eos_R = self.eos_a, self.eos_b, self.eos_R
         p.acentric, p.T_over_Tc = self.acentric, self.T_over_Tc
         p.kappa_tilde = self.kappa_tilde
         p.nu_liquid, p.nu_vapour = self.nu_liquid, self.nu_vapour
         p.rho_liquid, p.rho_vapour = self.rho_liquid, self.rho_vapour
+        g = list(self.body_accel) + [0.0] * (3 - len(self.body_accel))
+        for k in range(3):
+            p.body_accel[k] = float(g[k])
+        p.target_W = float(self.target_W)
         return p
 
 
@@ -284,6 +297,13 @@ def elmrt_coexistence(p: Params):
     rv, rl, ps = ctypes.c_double(), ctypes.c_double(), ctypes.c_double()
     _check(lib().elmrt_coexistence(ctypes.byref(cp), ctypes.byref(rv), ctypes.byref(rl), ctypes.byref(ps)))
     return rv.value, rl.value, ps.value
+
+
+def elmrt_kappa_for_width(p: Params, W: float) -> float:
+    cp = p.c()
+    out = ctypes.c_double()
+    _check(lib().elmrt_kappa_for_width(ctypes.byref(cp), float(W), ctypes.byref(out)))
+    return out.value
 
 
 def elmrt_pressure(p: Params, rho: np.ndarray) -> np.ndarray:

@@ -34,9 +34,10 @@ def test_header_symbols_exported():
 
 
 def test_params_struct_size_matches_header():
-    # layout from the header: u32, 3 x i32, 3 x i64, 3 x i32, i32, 10 x f64;
-    # the library itself rejects a struct_size other than its sizeof
-    assert ctypes.sizeof(E.elmrt_params) == 4 + 12 + 24 + 12 + 4 + 10 * 8
+    # layout from the header: u32, 3 x i32, 3 x i64, 3 x i32, i32, 10 x f64,
+    # 3 x f64 (body acceleration), f64 (target width); the library itself
+    # rejects a struct_size other than its sizeof
+    assert ctypes.sizeof(E.elmrt_params) == 4 + 12 + 24 + 12 + 4 + 10 * 8 + 3 * 8 + 8
     E.elmrt_workspace_bytes(E.Params(lattice=0, n=(8, 8, 1)))
 
 
@@ -62,6 +63,10 @@ def test_workspace_bytes(w):
     (dict(nu_liquid=0.0), "viscosities"),
     (dict(nu_liquid=0.01, nu_vapour=0.1, rho_liquid=0.1, rho_vapour=1.0), "rho_liquid"),
     (dict(bc=(2, 0, 0)), "bc"),
+    (dict(body_accel=(0.0, 0.0, 1e-5)), "body_accel"),
+    (dict(body_accel=(float("nan"), 0.0, 0.0)), "body_accel"),
+    (dict(target_W=-1.0), "target_W"),
+    (dict(target_W=5.0, kappa_tilde=0.01), "not both"),
 ])
 def test_invalid_params_rejected(change, msg):
     base = dict(lattice=E.ELMRT_D2Q9, n=(16, 16, 1))
@@ -174,3 +179,26 @@ def test_null_handles_rejected_without_a_device():
     }
     for name, call in calls.items():
         assert call() == E.ELMRT_E_INVALID, name
+
+
+def test_unknown_readings_rejected():
+    p = E.Params(lattice=0, n=(16, 16, 1)).c()
+    p.readings = 4
+    out = ctypes.c_size_t()
+    assert E.lib().elmrt_workspace_bytes(ctypes.byref(p), ctypes.byref(out)) == E.ELMRT_E_INVALID
+    assert "readings" in E.elmrt_last_error()
+
+
+@pytest.mark.parametrize("tr", [0.592454, 0.7, 0.8, 0.9])
+@pytest.mark.parametrize("eos", [W.EOS_A, W.EOS_B])
+def test_kappa_for_width_matches_oracle(tr, eos):
+    """The library's kappa~(W) (closed-form antiderivative of P/rho^2, golden
+    section on the potential's peak) against the oracle's (Simpson
+    quadrature, scan), host FP64."""
+    p = E.Params(lattice=0, n=(16, 16, 1), T_over_Tc=tr, **eos)
+    for Wd in (5.0, 12.0):
+        k_lib = E.elmrt_kappa_for_width(p, Wd)
+        k_ora = O.kappa_for_width(eos["eos_a"], eos["eos_b"], eos["eos_R"], eos["acentric"], tr, Wd)
+        assert abs(k_lib / k_ora - 1) < 1e-7, (k_lib, k_ora)
+    with pytest.raises(E.ElmrtError):
+        E.elmrt_kappa_for_width(p, 0.0)

@@ -116,7 +116,7 @@ def test_fill_budget_takes_turns(policy):
     srv.set_policy(policy)
     a = srv.submit(E.params_for(w1), *W.initial_fields(w1), 12)
     b = srv.submit(E.params_for(w2), *W.initial_fields(w2), 8)
-    srv.run(2)          # the first round admits both, the second advances one
+    srv.run(1)          # the first pass admits both and advances one
     first, second = (a, b) if policy in (0, 2) else (b, a)
     assert srv.job(first)[2] == 4 and srv.job(second)[2] == 0
     while srv.run(1) != (0, 0):
