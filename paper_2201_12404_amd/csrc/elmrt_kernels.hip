@@ -248,6 +248,21 @@ __device__ __forceinline__ float root<float>(float x) { return __builtin_amdgcn_
 template <>
 __device__ __forceinline__ double root<double>(double x) { return sqrt(x); }
 
+// Square root of a normal positive x (or 0) for psi: the hardware reciprocal
+// square root estimate y, one Goldschmidt step on (s, h) = (x y, y/2), which
+// doubles the correct bits, and one Newton correction of s (error <= 1 ulp;
+// the correctly rounded sqrt adds a second correction and denormal scaling).
+__device__ __forceinline__ double root_normal(double x)
+{
+    if (!(x > 0.0)) return 0.0;
+    const double y = __builtin_amdgcn_rsq(x);
+    double s = x * y, h = 0.5 * y;
+    const double r = fma(-s, h, 0.5);
+    s = fma(s, r, s);
+    h = fma(h, r, h);
+    return fma(fma(-s, s, x), h, s);
+}
+
 // psi = sqrt(|P - P0|) (Sec. 2.3), P from the Peng-Robinson EOS (Sec. 3.1),
 // P0 = rho cs^2; the sign is the sign of the psi term of the force.
 template <typename T>
@@ -258,7 +273,9 @@ __device__ __forceinline__ T psi_signed(T r, const Phys<T>& ph)
     const T d2 = T(1) + T(2) * ph.b * r - ph.b * ph.b * r * r;
     const T P = (r * ph.RT * d2 - ph.aal * r * r * d1) * rcp<T>(d1 * d2);
     const T d = P - r * (T(1) / T(3));
-    const T s = root<T>(fabs(d));
+    T s;
+    if constexpr (sizeof(T) == 8) s = root_normal(fabs(d));
+    else s = root<T>(fabs(d));
     return d > T(0) ? -s : s;
 }
 
@@ -814,8 +831,13 @@ __device__ __forceinline__ void collide_tile(int b, const T* __restrict__ cur, T
     constexpr int NT = TX * TY;
     constexpr int NE = (HX * HY + NT - 1) / NT;   // halo entries staged per thread and plane
     constexpr int MA = D - 1;
-    __shared__ double tpsi[5][HY][HX];   // signed psi, FP64
-    __shared__ T trho[5][HY][HX];        // rho as stored (exact in FP64)
+    // Six plane slots for the five-plane window of the stencils: the plane
+    // staged while a slower wave still computes the previous plane goes to
+    // the slot that window does not read, so one barrier per plane (after
+    // staging) orders every LDS access.
+    constexpr int NS = 6;
+    __shared__ double tpsi[NS][HY][HX];  // signed psi, FP64
+    __shared__ T trho[NS][HY][HX];       // rho as stored (exact in FP64)
 
     const TileCoords t = tile_of<D, TX, TY>(g, b, bx, by, tm);
     const int tx = threadIdx.x;
@@ -878,13 +900,13 @@ __device__ __forceinline__ void collide_tile(int b, const T* __restrict__ cur, T
     // Per plane: the density loads of the plane entering the window go out
     // first (staging waits only for them), then the Q population pulls and the
     // flux loads for Phi; psi is computed and staged while those are in flight.
-    // LDS slot of plane m - 2 is (m - m0) mod 5: a rotation counter kept
+    // LDS slot of plane m - 2 is (m - m0) mod 6: a rotation counter kept
     // uniform (scalar), so that the slot arithmetic is not done per lane
     int rot = 0;
 #pragma unroll 1
     for (int m = t.m0; m < t.m1; ++m) {
         const int r0 = __builtin_amdgcn_readfirstlane(rot);
-        rot = (r0 == 4) ? 0 : r0 + 1;
+        rot = (r0 == NS - 1) ? 0 : r0 + 1;
         PlanePull P;
         plane_setup<D, T>(g, m, P);
         T f[Q];
@@ -911,7 +933,7 @@ __device__ __forceinline__ void collide_tile(int b, const T* __restrict__ cur, T
                 }
             }
         }
-        stage_plane(r0 == 0 ? 4 : r0 - 1, rn);
+        stage_plane(r0 + 4 >= NS ? r0 + 4 - NS : r0 + 4, rn);   // plane m + 2
         __syncthreads();
         if (active) {
             // flux differences for Phi, formed as soon as the loads are back so
@@ -937,7 +959,7 @@ __device__ __forceinline__ void collide_tile(int b, const T* __restrict__ cur, T
 
             int sl[5];
 #pragma unroll
-            for (int d = 0; d < 5; ++d) sl[d] = (r0 + d >= 5) ? r0 + d - 5 : r0 + d;   // plane m + d - 2
+            for (int d = 0; d < 5; ++d) sl[d] = (r0 + d >= NS) ? r0 + d - NS : r0 + d;   // plane m + d - 2
             const int hy0 = (D == 3) ? ty + 2 : 0;
             const double c0psi = tpsi[sl[2]][hy0][tx + 2];
             // force stencils (Sec. 2.3): sums of 3 w_i c_i times
@@ -1027,7 +1049,6 @@ __device__ __forceinline__ void collide_tile(int b, const T* __restrict__ cur, T
                 for (int i = 0; i < Q; ++i) bst<T, kStream>(R, L.ip, (uint32_t)i * pb, f[i]);
             }
         }
-        __syncthreads();
     }
 }
 
