@@ -23,3 +23,13 @@ def test_smallest_golden_reproduces():
     assert np.array_equal((rho[None] * u).astype(np.float32).astype(np.float64), g["j"])
     np.testing.assert_allclose(sums, g["sums"], rtol=1e-15, atol=0)
 
+
+
+def test_goldens_cover_every_case():
+    """Every case and checkpoint has its golden file, of the stated step."""
+    import os
+    for name in PC.cases():
+        for step in (PC.STEPS,) + tuple(PC.CHECKPOINTS.get(name, ())):
+            path = PC.golden_path(name, step)
+            assert os.path.exists(path), path
+            assert PC.load_golden(name, step)["steps"] == step
