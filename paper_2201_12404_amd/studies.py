@@ -291,7 +291,8 @@ def surface_tension(tr: float, radii=(30.0, 45.0), a: float = 0.003, **kw) -> fl
 
 
 def impact_case(R0: float, u0: float, nu_l: float, D: int = 2, ratio: int = 1000, nu_ratio: float = 15.0,
-                film: float | None = None, width: float = 5.0, extent=None, precision: int = 0) -> W.Workload:
+                film: float | None = None, width: float = 5.0, extent=None, precision: int = 0,
+                a: float = 0.003) -> W.Workload:
     """Drop impact on a film (Sec. 3.2, 3.3) with drop radius R0, impact
     speed u0 and liquid kinematic viscosity nu_l (lattice units).
 
@@ -300,7 +301,10 @@ def impact_case(R0: float, u0: float, nu_l: float, D: int = 2, ratio: int = 1000
     walls, bounce-back walls normal to the last axis, the drop centred over
     the axis with a gap of 2 W above the film, vapour/liquid kinematic
     viscosity ratio nu_ratio (15 for air/water), density ratio 'ratio' by the
-    Maxwell table of EOS set B."""
+    Maxwell table of EOS set B.  'a' is the attraction parameter of the
+    Peng-Robinson EOS (b = 0.095); kappa~ scales with it, which keeps the
+    interface width and the coexistence densities and scales the surface
+    tension roughly with a."""
     tr = W.TR_OF_RATIO[ratio]
     rv, rl = W.COEX_B_TABLE[tr]
     if extent is None:
@@ -310,8 +314,8 @@ def impact_case(R0: float, u0: float, nu_l: float, D: int = 2, ratio: int = 1000
     zc = h + R0 + 2.0 * width
     centre = tuple((k - 1) / 2 for k in n[:-1]) + (zc,)
     return W.Workload(name=f"impact-R{R0:g}-U{u0:g}-nu{nu_l:g}-d{D}", lattice=0 if D == 2 else 1, n=n,
-                      bc=(0,) * (D - 1) + (1,), precision=precision, eos=W.EOS_B, T_over_Tc=tr,
-                      kappa_tilde=W.kappa_w5(tr), nu_liquid=nu_l, nu_vapour=nu_ratio * nu_l, rho_v=rv, rho_l=rl,
+                      bc=(0,) * (D - 1) + (1,), precision=precision, eos=_eos(a), T_over_Tc=tr,
+                      kappa_tilde=kappa_for(tr, a), nu_liquid=nu_l, nu_vapour=nu_ratio * nu_l, rho_v=rv, rho_l=rl,
                       kind="impact", radius=R0, width=width, film=h, centre=centre, u_impact=u0)
 
 
@@ -437,17 +441,25 @@ def fit_sqrt_offset(t_tau: np.ndarray, r_R0: np.ndarray, lo: float = 0.05, hi: f
 PAPER_2D_IMPACTS = ((57.0, 4000.0), (93.0, 4000.0), (238.0, 4000.0), (93.0, 100.0))   # (We, Re), Sec. 3.2
 
 
+IMPACT_A = 5e-4   # EOS attraction of the (We, Re) impacts: sigma = 0.0552 at ratio 1000
+
+
 def crown_sweep(cases=PAPER_2D_IMPACTS, R0: float = 100.0, sigma: float | None = None, D: int = 2,
-                t_end: float = 1.0, samples: int = 25, window=(0.04, 0.25), **kw) -> list:
+                t_end: float = 1.0, samples: int = 25, window=(0.04, 0.25), a: float = IMPACT_A, **kw) -> list:
     """Crown-radius histories of impacts at the (We, Re) pairs, each fitted
     to r / R0 = c (t / tau)^n over the window of t / tau; sigma defaults to
-    the Laplace-law surface tension of the EOS at the impact temperature.
-    A case that goes unstable is reported with stable = False."""
+    the Laplace-law surface tension of the EOS (attraction a, kappa~ scaled
+    with it) at the impact temperature.  The paper gives no lattice value of
+    sigma; the lower a, the lower sigma and hence U0 at a given We, and with
+    it nu = 2 U0 R0 / Re.  At a = 0.003 (sigma = 0.185) the case We 238 needs
+    U0 = 0.158 and We 93, Re 100 a vapour viscosity of 3, and both diverge at
+    R0 = 100; at a = 5e-4 all four cases of Sec. 3.2 run.  A case that goes
+    unstable is reported with stable = False."""
     if sigma is None:
-        sigma = surface_tension(W.TR_OF_RATIO[kw.get("ratio", 1000)])
+        sigma = surface_tension(W.TR_OF_RATIO[kw.get("ratio", 1000)], a=a)
     out = []
     for We, Re in cases:
-        w = impact_we_re(We, Re, R0, sigma, D=D, **kw)
+        w = impact_we_re(We, Re, R0, sigma, D=D, a=a, **kw)
         rec = dict(We=We, Re=Re, R0=R0, D=D, u0=w.u_impact, nu_l=w.nu_liquid, sigma=sigma, stable=True)
         try:
             h = crown_history(w, t_end=t_end, samples=samples)
