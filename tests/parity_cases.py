@@ -29,8 +29,9 @@ import numpy as np
 from paper_2201_12404_amd import workloads as W
 
 STEPS = 1000
-# earlier instants stored as well, at which the flow passes no singular event
-# (no film rupture or merging under way), where every norm is held to 1e-5
+# earlier instants stored as well: the 3-D impact at step 500, where every
+# norm is held to 1e-5, and the 2-D impact at step 600, where its moments are
+# (its velocity is ill-conditioned at every instant from the approach on)
 CHECKPOINTS = {"c2-full": (600,), "c3-96": (500,)}
 GOLDEN_DIR = os.path.join(os.path.dirname(os.path.abspath(__file__)), "golden")
 C5_D2Q9 = (33, 56, 3, 35, 59, 78)   # indices in the served stream

@@ -14,15 +14,18 @@ The oracle's fields come from tests/golden/parity_<case>.npz (written by
 tests/golden/make_parity_goldens.py, which calls only the oracle) for the
 impacts, and from the oracle run in the test for the batch members.
 
-Bars.  Every case: e_rho, e_j (max norm on j = rho u) and l2_j <= 1e-5.  The
-bare velocity u = j / rho: e_u and l2_u <= 1e-5 where the flow has no
-singular event (the static drops of the batch, the served jobs still before
-contact), else <= 3 x the conditioning spread of that case.  The spread is
-what FP32-sized perturbations do to the exact method: the FP64 build (equal to
-the oracle within 1e-12) run once plainly and once with every population
+Bars.  Each norm -- e_rho, e_j (max norm on j = rho u), l2_j, and e_u, l2_u
+on the bare velocity u = j / rho -- is held to max(1e-5, 3 x the
+conditioning spread of that case at that instant).  The batch members
+(static drops) and the 3-D impact at step 500 are held to 1e-5 on every
+norm, the 2-D impact at step 600 on its moments.  The spread is what
+FP32-sized perturbations do to the exact method: the FP64 build (equal to the
+oracle within 1e-12) run once plainly and once with every population
 multiplied by (1 + 2^-24 eta), eta uniform in [-1, 1], before every step; it
 is measured by this module (test_conditioning_spread) and recorded in SPREAD
-below.
+below.  Where a drop meets a film or another drop, the draining vapour layer
+makes it exceed 1e-5 on u, and on the max norms of rho and j through a
+rupture.
 """
 import os
 import sys
@@ -59,6 +62,15 @@ SPREAD = {
 }
 
 
+# The same spread at the earlier stored instants, where measured.  On the 2-D
+# impact the velocity spread stays near 1e-5 or above from the approach of the
+# drop (the draining vapour layer) to step 1000: 6.3e-4 at step 200, 1.6e-5
+# at 600, 1.2e-5 at 700 (e_u), while the moments' spread at 600 is ~2e-6.
+SPREAD_AT = {
+    ('c2-full', 600): {'e_rho': 2.17e-06, 'e_j': 2.95e-06, 'l2_j': 1.55e-06, 'e_u': 1.58e-05, 'l2_u': 1.03e-05},
+}
+
+
 def bar(name, k):
     return max(1e-5, 3.0 * SPREAD.get(name, {}).get(k, 0.0))
 
@@ -88,11 +100,16 @@ def fmt(d):
     return " ".join(f"{k}={v:.3e}" for k, v in d.items())
 
 
-def check(name, n, strict=False):
-    """Every norm <= 1e-5 (strict), else <= max(1e-5, 3 x the case's spread)."""
+def check(name, n, strict=False, spread=None):
+    """Every norm <= 1e-5 (strict), else <= max(1e-5, 3 x the case's spread);
+    with 'spread' given: the moments' norms <= 1e-5 and those of u <=
+    max(1e-5, 3 x spread)."""
     say(f"{name}: {fmt(n)}")
     for k in NORMS:
-        lim = 1e-5 if strict else bar(name, k)
+        if spread is not None:
+            lim = max(1e-5, 3.0 * spread[k]) if k in ("e_u", "l2_u") else 1e-5
+        else:
+            lim = 1e-5 if strict else bar(name, k)
         assert n[k] <= lim, (name, k, n[k], lim)
 
 
@@ -103,7 +120,7 @@ def golden(name, step=None):
     return PC.load_golden(name, step)
 
 
-def compare_with_golden(name, w, rho, u, sums, step=PC.STEPS, strict=False):
+def compare_with_golden(name, w, rho, u, sums, step=PC.STEPS, strict=False, spread=None):
     g = golden(name, step)
     assert g["steps"] == step
     j = rho[None, :] * u
@@ -113,7 +130,7 @@ def compare_with_golden(name, w, rho, u, sums, step=PC.STEPS, strict=False):
     n = norms(rho, j, g["rho"], g["j"])
     # global sums of the whole grid (FP64 sums on both sides)
     n["mass"] = abs(sums[0] / g["sums"][0] - 1)
-    check(name, n, strict)
+    check(name, n, strict, spread)
     assert n["mass"] <= 1e-6
 
 
@@ -139,15 +156,17 @@ def test_impact_real_shape_1000_steps(name):
 
 
 @pytest.mark.parametrize("name", ["c2-full", "c3-96"])
-def test_impact_real_shape_regular_instant(name):
-    """The same runs at an instant without a singular event (the 2-D impact
-    at step 600, after the first rupture has relaxed; the 3-D impact at step
-    500): every norm within 1e-5 of the oracle."""
+def test_impact_real_shape_checkpoint(name):
+    """The same runs at an earlier stored instant: the 3-D impact at step
+    500, every norm within 1e-5 of the oracle; the 2-D impact at step 600,
+    where the moments' conditioning spread is ~2e-6: e_rho, e_j and l2_j
+    within 1e-5, the velocity norms within 3 x their spread there (1.6e-5 and
+    1.0e-5, SPREAD_AT)."""
     w = PC.cases()[name]
     (step,) = PC.CHECKPOINTS[name]
     say(f"[gpu] {name} {w.name} n={w.n} {step} steps")
     rho, u, sums = run_alone(w, step)
-    compare_with_golden(name, w, rho, u, sums, step=step, strict=True)
+    compare_with_golden(name, w, rho, u, sums, step=step, strict=True, spread=SPREAD_AT.get((name, step)))
 
 
 def test_batch_members_1000_steps():
