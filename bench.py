@@ -251,7 +251,7 @@ def served_replay(jobs, inputs, policy: int, fill: int, chunk: int, pool_gib: fl
             "mlups": round(lu / t_end / 1e6, 1), "makespan_s": round(t_end, 3), "evicted_jobs": evicted}
 
 
-def served_vs_plain(count: int, step_scale: float, fill: int = 4 << 20, chunk: int = 200):
+def served_vs_plain(count: int, step_scale: float, fill: int = 2 << 20, chunk: int = 200):
     """Plain FIFO against the request loop in arrival order (the server's
     default) and with least remaining work first, on the same jobs."""
     jobs, inputs = served_jobs(count, step_scale)

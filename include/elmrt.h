@@ -317,7 +317,7 @@ void elmrt_destroy(elmrt_sim* s);
  * order (elmrt_server_set_policy: arrival order -- the default -- least
  * remaining work -- cells x steps -- first, or that with the oldest job
  * always first) until
- * their cells reach a fill budget (elmrt_server_set_fill, default 2^22
+ * their cells reach a fill budget (elmrt_server_set_fill, default 2^21
  * cells, at least one job), and advances them as one batch per lattice and
  * precision (the elmrt_batch_* machinery, without graphs): the costliest
  * batch by chunk_steps, a cheaper one by proportionally more steps (bytes

@@ -143,7 +143,7 @@ struct elmrt_server {
     uint32_t* flags = nullptr;
     std::vector<int> free_slots;
     int64_t chunk = 100;
-    int64_t fill = 4 << 20;             // cells advanced per round (at least one job)
+    int64_t fill = 2 << 20;             // cells advanced per round (at least one job)
     int32_t policy = 0;                 // 0 arrival order, 1 shortest remaining work first,
                                         // 2 as 1 with the oldest job in every round
     int64_t next_id = 1;
