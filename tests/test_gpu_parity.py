@@ -6,22 +6,17 @@ max|rho_ora|; e_j and l2_j the same in the max and 2-norm on the momentum
 density j = rho u (the first moment of f); e_u and l2_u on the bare velocity
 u = j / rho.
 
-Bars.  FP64 build: e_rho, e_u <= 1e-12.  FP32 build, after 1000 steps:
-relative 1e-5 on the moments of f, e_rho <= 1e-5 and l2_j <= 1e-5, in every
-case; in flows without a singular event also e_u and l2_u <= 1e-5 (the 2-D
-drop approaching the film).
+Bars.  FP64 build: e_rho, e_u <= 1e-12.  FP32 build: every norm <= 1e-5 in
+flows without a singular event (the 2-D drop approaching the film); through
+an impact each norm <= max(1e-5, 3 x the case's conditioning spread).
 
-Velocity bars at singular events.  Once the drop touches the film the flow
-passes through instants where a thin vapour layer drains and ruptures; there
-u = j / rho in cells of density ~0.01-0.04 amplifies any perturbation.  Two
-FP32 builds of this library whose arithmetic differs only in the order of a
-few FP32 operations (1-ulp differences in 98 of 294912 values after 10
-steps) disagree with each other by l2_u = 2.4e-5 at step 800 and 1.6e-5 at
-step 1000 of the 2-D impact below, and the FP64 oracle perturbed by
-FP32-sized noise (relative 6e-8, every step) departs from itself by up to
-e_u = 1.4e-4, l2_u = 6e-6 at such instants.  The velocity bars there are
-l2_u <= 1e-4 and e_u <= 1e-3: what the problem's conditioning leaves to any
-FP32-storage implementation, an order of magnitude above what is seen.
+Conditioning.  Once the drop nears the film the flow passes through instants
+where a thin vapour layer drains and ruptures; there u = j / rho in cells of
+density ~0.01-0.04 amplifies any perturbation.  The conditioning spread is
+the largest departure, over four noise seeds, of the FP64 build (equal to the
+oracle within 1e-12) with every population multiplied by (1 + 2^-24 eta),
+eta uniform in [-1, 1], before every step, from the plain FP64 build
+(measured on the MI355X; the real-shape module re-measures its cases).
 """
 import os
 import sys
@@ -35,6 +30,22 @@ from paper_2201_12404_amd import elmrt as E
 from paper_2201_12404_amd import workloads as W
 
 pytestmark = pytest.mark.gpu
+
+# conditioning spread of the scaled impacts below (FP64 build with FP32-sized
+# noise against the plain FP64 build, four seeds, measured on the MI355X)
+SPREAD = {
+    "impact-d2q9-256x128-fp32": {"e_rho": 7.99e-07, "e_j": 1.83e-06, "l2_j": 1.04e-06, "e_u": 3.07e-05,
+                                 "l2_u": 2.59e-06},
+    "impact-d3q27-72x40x40-fp32": {"e_rho": 4.54e-07, "e_j": 6.59e-06, "l2_j": 1.14e-06, "e_u": 7.49e-05,
+                                   "l2_u": 6.9e-06},
+}
+
+
+def check_spread(name, n):
+    """Every norm <= max(1e-5, 3 x the conditioning spread of the case)."""
+    for k, v in SPREAD[name].items():
+        lim = max(1e-5, 3.0 * v)
+        assert n[k] <= lim, (name, k, n[k], lim)
 
 
 def say(*a):
@@ -159,8 +170,7 @@ def test_impact_2d_fp32_scaled_1000_steps():
     rho_o, u_o, _, _, _ = run_oracle(w, 1000)
     n = fp32_norms(rho_g, u_g, rho_o, u_o)
     say("impact 2d fp32: " + fmt(n))
-    assert n["e_rho"] < 1e-5 and n["l2_j"] < 1e-5
-    assert n["l2_u"] < 1e-4 and n["e_u"] < 1e-3
+    check_spread(w.name, n)
 
 
 def test_approach_2d_fp32_1000_steps():
@@ -186,8 +196,7 @@ def test_impact_3d_fp32_scaled():
     rho_o, u_o, _, _, _ = run_oracle(w, w.steps)
     n = fp32_norms(rho_g, u_g, rho_o, u_o)
     say("impact 3d fp32: " + fmt(n))
-    assert n["e_rho"] < 1e-5 and n["l2_j"] < 1e-5
-    assert n["l2_u"] < 1e-4 and n["e_u"] < 1e-3
+    check_spread(w.name, n)
 
 
 @pytest.mark.parametrize("D,shapes", [(3, [(64, 4, 16), (32, 8, 5), (64, 2, 7), (128, 2, 64), (64, 4, 1),
