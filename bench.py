@@ -107,7 +107,14 @@ def cpu_baseline(w, budget_s: float = 20.0):
         if elapsed > 0.6 * budget_s:
             break
     mlups = sx * sy * sz * steps / elapsed / 1e6
-    return {"value": round(mlups, 4), "unit": "MLUPS", "cores": threads, "kind": "oracle",
+    cpu = "unknown"
+    try:
+        with open("/proc/cpuinfo") as fh:
+            cpu = next((ln.split(":", 1)[1].strip() for ln in fh if ln.startswith("model name")), cpu)
+    except OSError:
+        pass
+    return {"value": round(mlups, 4), "unit": "MLUPS", "cores": threads, "kind": "oracle", "cpu": cpu,
+            "affinity": len(os.sched_getaffinity(0)),
             "sample": f"{steps} step(s) of a {sx}x{sy}x{sz} block of the 256^3 impact state "
                       f"(FP64 oracle, OpenMP over cells), {elapsed:.1f} s"}
 
