@@ -443,6 +443,11 @@ PAPER_2D_IMPACTS = ((57.0, 4000.0), (93.0, 4000.0), (238.0, 4000.0), (93.0, 100.
 
 IMPACT_A = 5e-4   # EOS attraction of the (We, Re) impacts: sigma = 0.0552 at ratio 1000
 
+# 3-D impacts of Sec. 3.3: We 82, 167, 328 over Re 3500..6900.  The paper
+# gives the range of Re only; a drop of fixed size and fluid has Re / sqrt(We)
+# constant, so Re = 6900 sqrt(We / 328).
+PAPER_3D_IMPACTS = tuple((we, round(6900.0 * (we / 328.0) ** 0.5)) for we in (82.0, 167.0, 328.0))
+
 
 def crown_sweep(cases=PAPER_2D_IMPACTS, R0: float = 100.0, sigma: float | None = None, D: int = 2,
                 t_end: float = 1.0, samples: int = 25, window=(0.04, 0.25), a: float = IMPACT_A, **kw) -> list:
@@ -465,6 +470,42 @@ def crown_sweep(cases=PAPER_2D_IMPACTS, R0: float = 100.0, sigma: float | None =
             h = crown_history(w, t_end=t_end, samples=samples)
             rec.update(t_tau=h["t_tau"], r_R0=h["r_R0"], steps=h["steps"])
             rec["n"], rec["c"] = fit_sqrt(h["t_tau"], h["r_R0"], *window)
+            rec["c_off"], rec["t_c"], rec["resid"] = fit_sqrt_offset(h["t_tau"], h["r_R0"], *window)
+        except E.ElmrtUnstable:
+            rec["stable"] = False
+        out.append(rec)
+    return out
+
+
+def paper_3d_impacts(R0: float = 80.0, cases=PAPER_3D_IMPACTS, a: float = IMPACT_A, kappa_scale: float = 2.0,
+                     sigma: float | None = None, t_end: float = 0.5, samples: int = 10, window=(0.05, 0.5),
+                     noisy_we: float = 328.0, progress=None) -> list:
+    """The 3-D drop impacts of Sec. 3.3 at the paper's size: R0 = 80 in a
+    14 R0 x 14 R0 x 6 R0 box (1120 x 1120 x 480 = 6.0e8 cells at R0 = 80,
+    140 GB of populations and fields in FP32), film h = 0.44 R0, density
+    ratio 1000, nu_v = 15 nu_l, EOS attraction a with kappa~ scaled with it
+    and by kappa_scale (2: an interface about sqrt(2) times wider than the
+    2-D cases', W ~ 7; the initial profiles take that width), 5 % white
+    noise on the liquid velocity at the largest We.  sigma defaults to the
+    Laplace-law surface tension at that a and kappa~.  Returns per case the
+    crown diameter history d / (2 R0) against t / tau and its fits (power
+    law, square root with a free origin).  A case that goes unstable is
+    reported with stable = False."""
+    tr = W.TR_OF_RATIO[1000]
+    if sigma is None:
+        sigma = surface_tension(tr, a=a, kappa=kappa_for(tr, a) * kappa_scale)
+    out = []
+    for We, Re in cases:
+        w = impact_we_re(We, Re, R0, sigma, D=3, a=a)
+        w = replace(w, kappa_tilde=w.kappa_tilde * kappa_scale, width=w.width * kappa_scale ** 0.5)
+        if We == noisy_we:
+            w = replace(w, noise_liquid=0.05, seed=1)
+        rec = dict(We=We, Re=Re, R0=R0, n=w.n, cells=w.N, u0=w.u_impact, nu_l=w.nu_liquid, sigma=sigma,
+                   stable=True)
+        try:
+            h = crown_history(w, t_end=t_end, samples=samples, progress=progress)
+            rec.update(t_tau=h["t_tau"], d_2R0=h["r_R0"], steps=h["steps"])
+            rec["n_fit"], rec["c"] = fit_sqrt(h["t_tau"], h["r_R0"], *window)
             rec["c_off"], rec["t_c"], rec["resid"] = fit_sqrt_offset(h["t_tau"], h["r_R0"], *window)
         except E.ElmrtUnstable:
             rec["stable"] = False

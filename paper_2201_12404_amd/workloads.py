@@ -114,6 +114,7 @@ class Workload:
     centre: tuple = ()
     u_impact: float = 0.0
     noise: float = 0.0      # uniform velocity noise amplitude
+    noise_liquid: float = 0.0   # impacts: Gaussian velocity noise in the liquid, std / u_impact
     seed: int = 0
     steps: int = 1000
 
@@ -160,6 +161,13 @@ def initial_fields(w: Workload):
         rho0 = w.rho_v + (w.rho_l - w.rho_v) * np.maximum(phi_f, phi_d)
         u0 = np.zeros((D, w.N))
         u0[D - 1] = -w.u_impact * phi_d
+        if w.noise_liquid > 0:
+            # white noise on the liquid's velocity, std noise_liquid * U0
+            # (Sec. 3.3, largest We), weighted by the liquid indicator
+            liquid = np.maximum(phi_f, phi_d)
+            rng = np.random.default_rng(w.seed)
+            for a in range(D):
+                u0[a] += rng.normal(0.0, w.noise_liquid * w.u_impact, w.N) * liquid
     else:
         raise ValueError(w.kind)
     if w.noise > 0:

@@ -114,3 +114,42 @@ def test_fixed_kappa_drops_differ_from_the_default_only_in_kappa():
             (ref.n, ref.radius, ref.width, ref.centre, ref.nu_liquid, ref.nu_vapour)
         assert w.kappa_tilde == k07
         assert (ref.kappa_tilde == k07) == (tr == 0.7)
+
+
+def test_paper_3d_impacts_groups_and_box():
+    """Sec. 3.3: We 82, 167, 328 over Re 3500..6900 with Re / sqrt(We)
+    constant (a fixed drop and fluid), R0 = 80 in a 14 R0 x 14 R0 x 6 R0 box
+    (6.0e8 cells) with h / 2R0 = 0.22."""
+    wes = [we for we, _ in S.PAPER_3D_IMPACTS]
+    res = [re for _, re in S.PAPER_3D_IMPACTS]
+    assert wes == [82.0, 167.0, 328.0]
+    assert res[-1] == 6900 and 3400 <= res[0] <= 3500
+    ratios = [re / np.sqrt(we) for we, re in S.PAPER_3D_IMPACTS]
+    assert max(ratios) / min(ratios) < 1.001
+    w = S.impact_we_re(82.0, res[0], 80.0, 0.06, D=3, a=5e-4)
+    assert w.n == (1120, 1120, 480) and w.N == 602112000
+    assert abs(w.film / (2 * w.radius) - 0.22) < 1e-12
+    assert abs(S.reynolds(w) - res[0]) < 1e-9 * res[0]
+
+
+def test_liquid_noise_is_seeded_gaussian_in_the_liquid_only():
+    """White noise on the liquid velocity (Sec. 3.3): std noise_liquid * U0
+    in the bulk liquid, none in the bulk vapour, the same for the same seed."""
+    from dataclasses import replace
+    w = S.impact_case(30.0, 0.05, 0.005)
+    w = replace(w, noise_liquid=0.05, seed=3)
+    rho, u = W.initial_fields(w)
+    rho2, u2 = W.initial_fields(w)
+    assert np.array_equal(u, u2) and np.array_equal(rho, rho2)
+    base_rho, base_u = W.initial_fields(replace(w, noise_liquid=0.0))
+    assert np.array_equal(rho, base_rho)
+    du = u - base_u
+    lam = (rho - w.rho_v) / (w.rho_l - w.rho_v)    # the liquid indicator
+    liquid, vapour = lam > 0.999, lam < 1e-9
+    assert liquid.sum() > 1000 and vapour.sum() > 1000
+    assert np.abs(du[:, vapour]).max() < 1e-8 * w.u_impact
+    s = du[:, liquid].std()
+    assert abs(s / (0.05 * w.u_impact) - 1) < 0.05
+    assert abs(du[:, liquid].mean()) < 0.1 * s
+    other = W.initial_fields(replace(w, seed=4))[1]
+    assert not np.array_equal(other, u)
