@@ -65,16 +65,17 @@ def algorithmic_bytes(D: int, es: int):
 
 
 def measured_traffic(tag: str, tiling):
-    """HBM bytes per collision launch from the committed rocprofv3 counter
-    summary, if it was taken on the current kernel source with this tiling."""
+    """HBM bytes per launch of the collision and of the moment kernel from the
+    committed rocprofv3 counter summary, if it was taken on the current kernel
+    source with this tiling; else (None, None)."""
     path = os.path.join(ROOT, "profiles", f"traffic_{tag}.json")
     if not os.path.exists(path):
-        return None
+        return None, None
     with open(path) as f:
         d = json.load(f)
     if d.get("kernel_source_sha") != kernel_source_hash() or d.get("tiling") != list(tiling):
-        return None
-    return d.get("bytes_per_launch")
+        return None, None
+    return d.get("bytes_per_launch"), d.get("k_macro", {}).get("bytes_per_launch")
 
 
 def cpu_baseline(w, budget_s: float = 20.0):
@@ -358,7 +359,7 @@ def main():
     avg_macro_s = ms_macro / args.steps / 1e3
     achieved = N * b_collide / avg_collide_s / 1e9
     tag = "collide_d3q27_fp32_256"
-    traffic = measured_traffic(tag, (tx, ty, tm))
+    traffic, traffic_macro = measured_traffic(tag, (tx, ty, tm))
     out = {
         "metric": "MLUPS (D3Q27 FP32 256^3 drop-impact step)",
         "value": round(mlups, 1),
@@ -376,6 +377,10 @@ def main():
                    "collision": "entropic", "density_ratio": 1000, "tiling": [tx, ty, tm],
                    "autotune_steps": tuned},
         "hbm_gbs_algorithmic_step": round(N * (b_macro + b_collide) / wall * args.steps / 1e9, 1),
+        # the step's HBM bytes counted by rocprofv3 (both kernels, committed
+        # counters on this source) over the measured time per step
+        "hbm_gbs_counted_step": (round((traffic + traffic_macro) / (ms_per_step / 1e3) / 1e9, 1)
+                                 if traffic and traffic_macro else None),
         "kernels_ms": {"moments": round(avg_macro_s * 1e3, 4), "collide": round(avg_collide_s * 1e3, 4)},
         "roofline": {
             "kernel": f"k_collide<3,float,{tx},{ty}>",
