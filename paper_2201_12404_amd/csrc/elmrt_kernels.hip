@@ -811,6 +811,94 @@ __device__ __forceinline__ void macro_tile(int b, const T* __restrict__ cur, T* 
     if (bad) atomicOr(flag, 1u);
 }
 
+// Moment pass with two cells per lane, (x, x + 1), for FP32 grids that are
+// periodic in x with an even width: each population pair comes in one 8-byte
+// load (half the load instructions of one cell per lane), the moments of each
+// cell are formed exactly as in macro_tile, so the fields are bitwise the
+// same.  A pair whose sources wrap around the row (x = 0 pulling from the
+// row's end, or x + 1 = nx - 1 pulling from its start) takes its second value
+// from a load of its own.
+using f32x2 = float __attribute__((ext_vector_type(2)));
+__device__ __forceinline__ f32x2 bld2(__amdgpu_buffer_rsrc_t r, uint32_t voff, uint32_t soff)
+{
+    return __builtin_bit_cast(f32x2, __builtin_amdgcn_raw_buffer_load_b64(r, (int)voff, (int)soff, 0));
+}
+
+template <int D>
+__device__ __forceinline__ void pull_m2_fast(const float* __restrict__ cur, const LanePull& L0, const LanePull& L1,
+                                             const PlanePull& P, float (&f0)[Lat<D>::Q], float (&f1)[Lat<D>::Q])
+{
+    constexpr int Q = Lat<D>::Q;
+    const uint32_t pb = opaque(P.bytes);
+    __amdgpu_buffer_rsrc_t R[3];
+    // 4 bytes beyond the block: the pair at its last cell (their second value
+    // is not used there; the block is followed by the next one, the other
+    // population buffer or the density field, all in the workspace)
+#pragma unroll
+    for (int k = 0; k < 3; ++k)
+        R[k] = block_rsrc(cur + (size_t)P.mo[k] * Q * P.stride, (uint32_t)Q * P.bytes + 4u);
+#pragma unroll
+    for (int i = 0; i < Q; ++i) {
+        const int cx = cx_<D>(i) + 1, cy = cy_<D>(i) + 1, cz = cz_<D>(i) + 1;
+        const int cm = (D == 3) ? cz : cy;
+        const uint32_t yo = (D == 3) ? L0.yo[cy] : 0u;
+        const uint32_t o0 = L0.xo[cx] + yo;
+        const f32x2 v = bld2(R[cm], o0, (uint32_t)i * pb);
+        f0[i] = v.x;
+        f1[i] = v.y;
+        if (cx != 1) {
+            const uint32_t o1 = L1.xo[cx] + yo;
+            if (o1 != o0 + 4u) f1[i] = bld<float>(R[cm], o1, (uint32_t)i * pb);
+        }
+    }
+}
+
+template <int D>
+__device__ __forceinline__ void macro_tile2(int b, const float* __restrict__ cur, float* __restrict__ rho_out,
+                                            float* __restrict__ q_out, unsigned* __restrict__ flag, const Grid& g,
+                                            int bx, int by, int tm, double rho_max, int q_momentum)
+{
+    constexpr int Q = Lat<D>::Q;
+    const TileCoords t = tile_of<D, kMacroTX, 1, true>(g, b, bx, by, tm);
+    const int x = t.x0 + 2 * (int)threadIdx.x;
+    const int y = (D == 3) ? t.y0 : 0;
+    if (x >= g.n[0]) return;   // the width is even: x + 1 is inside too
+    LanePull L0, L1;
+    lane_setup<D, float>(g, x, y, L0);
+    lane_setup<D, float>(g, x + 1, y, L1);
+    const bool clear = tile_clear<D, kMacroTX, 1>(g, t.x0, t.y0);
+    bool bad = false;
+#pragma unroll 1
+    for (int m = t.m0; m < t.m1; ++m) {
+        PlanePull P;
+        plane_setup<D, float>(g, m, P);
+        float f0[Q], f1[Q];
+        if (clear && P.mok[0] && P.mok[2]) {
+            pull_m2_fast<D>(cur, L0, L1, P, f0, f1);
+        } else {
+            pull_m<D, float, false>(cur, L0, P, f0);
+            pull_m<D, float, false>(cur, L1, P, f1);
+        }
+        double rho0, j0[3], rho1, j1[3];
+        moments<D, float, double>(f0, rho0, j0);
+        moments<D, float, double>(f1, rho1, j1);
+        const size_t mself = (size_t)P.m * P.stride;
+        // pairs of 8-byte-aligned values (x and the width are even)
+        pst<f32x2, true>(plane_ptr(rho_out + mself), L0.ip, f32x2{(float)rho0, (float)rho1});
+        const double inv0 = rcp<double>(rho0), inv1 = rcp<double>(rho1);
+#pragma unroll
+        for (int a = 0; a < D; ++a) {
+            const double u0 = j0[a] * inv0, u1 = j1[a] * inv1;
+            const float q0 = (float)(q_momentum ? j0[a] : j0[a] * u0 * u0);
+            const float q1 = (float)(q_momentum ? j1[a] : j1[a] * u1 * u1);
+            pst<f32x2, true>(plane_ptr(q_out + (size_t)a * g.N + mself), L0.ip, f32x2{q0, q1});
+        }
+        bad = bad || !(rho0 > 0.0) || !isfinite(rho0) || rho0 >= rho_max;
+        bad = bad || !(rho1 > 0.0) || !isfinite(rho1) || rho1 >= rho_max;
+    }
+    if (bad) atomicOr(flag, 1u);
+}
+
 // Fused stencil + collision pass.
 // Occupancy target of the collision kernel: 3 waves per SIMD (<= 168 VGPRs)
 // for D3Q27 in FP32, where it lowers the kernel time by ~12% against the
@@ -1072,6 +1160,16 @@ __global__ __launch_bounds__(TX* TY) void k_macro(const T* __restrict__ cur, T* 
                                                   int bx, int by, int tm, double rho_max, int q_momentum)
 {
     macro_tile<D, T, TX, TY>((int)blockIdx.x, cur, rho_out, q_out, flag, g, bx, by, tm, rho_max, q_momentum);
+}
+
+// Two cells per lane: kMacroTX / 2 lanes per 256-cell row (macro_tile2).
+template <int D>
+__global__ __launch_bounds__(kMacroTX / 2) void k_macro2(const float* __restrict__ cur, float* __restrict__ rho_out,
+                                                         float* __restrict__ q_out, unsigned* __restrict__ flag,
+                                                         Grid g, int bx, int by, int tm, double rho_max,
+                                                         int q_momentum)
+{
+    macro_tile2<D>((int)blockIdx.x, cur, rho_out, q_out, flag, g, bx, by, tm, rho_max, q_momentum);
 }
 
 template <int D, typename T, int TX, int TY>
@@ -1448,6 +1546,14 @@ hipError_t macro_t(const Launch& L, const void* cur, void* rho, void* q, unsigne
 {
     const Tiling t = macro_tiling(D, L.g);
     if (t.blocks <= 0 || t.blocks > 0x7fffffffLL) return hipErrorInvalidConfiguration;
+    if constexpr (sizeof(T) == 4) {
+        if (!L.g.wall[0] && L.g.n[0] % 2 == 0) {
+            hipLaunchKernelGGL((k_macro2<D>), dim3((unsigned)t.blocks), dim3(kMacroTX / 2, 1), 0, L.stream,
+                               (const float*)cur, (float*)rho, (float*)q, flag, L.g, t.bx, t.by, t.tm, rho_max,
+                               q_momentum);
+            return hipGetLastError();
+        }
+    }
     hipLaunchKernelGGL((k_macro<D, T, kMacroTX, 1>), dim3((unsigned)t.blocks), dim3(kMacroTX, 1), 0, L.stream,
                        (const T*)cur, (T*)rho, (T*)q, flag, L.g, t.bx, t.by, t.tm, rho_max, q_momentum);
     return hipGetLastError();
