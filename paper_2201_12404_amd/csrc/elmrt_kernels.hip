@@ -816,8 +816,8 @@ __device__ __forceinline__ void macro_tile(int b, const T* __restrict__ cur, T* 
 // load (half the load instructions of one cell per lane), the moments of each
 // cell are formed exactly as in macro_tile, so the fields are bitwise the
 // same.  A pair whose sources wrap around the row (x = 0 pulling from the
-// row's end, or x + 1 = nx - 1 pulling from its start) takes its second value
-// from a load of its own.
+// row's end, or x + 1 = nx - 1 pulling from its start) takes two 4-byte
+// loads instead, so that no load reaches into the next row's cache lines.
 using f32x2 = float __attribute__((ext_vector_type(2)));
 __device__ __forceinline__ f32x2 bld2(__amdgpu_buffer_rsrc_t r, uint32_t voff, uint32_t soff)
 {
@@ -831,24 +831,28 @@ __device__ __forceinline__ void pull_m2_fast(const float* __restrict__ cur, cons
     constexpr int Q = Lat<D>::Q;
     const uint32_t pb = opaque(P.bytes);
     __amdgpu_buffer_rsrc_t R[3];
-    // 4 bytes beyond the block: the pair at its last cell (their second value
-    // is not used there; the block is followed by the next one, the other
-    // population buffer or the density field, all in the workspace)
 #pragma unroll
-    for (int k = 0; k < 3; ++k)
-        R[k] = block_rsrc(cur + (size_t)P.mo[k] * Q * P.stride, (uint32_t)Q * P.bytes + 4u);
+    for (int k = 0; k < 3; ++k) R[k] = block_of<D, float>(cur, P, P.mo[k]);
 #pragma unroll
     for (int i = 0; i < Q; ++i) {
         const int cx = cx_<D>(i) + 1, cy = cy_<D>(i) + 1, cz = cz_<D>(i) + 1;
         const int cm = (D == 3) ? cz : cy;
         const uint32_t yo = (D == 3) ? L0.yo[cy] : 0u;
         const uint32_t o0 = L0.xo[cx] + yo;
-        const f32x2 v = bld2(R[cm], o0, (uint32_t)i * pb);
-        f0[i] = v.x;
-        f1[i] = v.y;
-        if (cx != 1) {
+        if (cx == 1) {
+            const f32x2 v = bld2(R[cm], o0, (uint32_t)i * pb);
+            f0[i] = v.x;
+            f1[i] = v.y;
+        } else {
             const uint32_t o1 = L1.xo[cx] + yo;
-            if (o1 != o0 + 4u) f1[i] = bld<float>(R[cm], o1, (uint32_t)i * pb);
+            if (o1 == o0 + 4u) {
+                const f32x2 v = bld2(R[cm], o0, (uint32_t)i * pb);
+                f0[i] = v.x;
+                f1[i] = v.y;
+            } else {   // wrapping pair: two loads, both inside the row
+                f0[i] = bld<float>(R[cm], o0, (uint32_t)i * pb);
+                f1[i] = bld<float>(R[cm], o1, (uint32_t)i * pb);
+            }
         }
     }
 }
