@@ -120,6 +120,29 @@ def cpu_baseline(w, budget_s: float = 20.0):
                       f"(FP64 oracle, OpenMP over cells), {elapsed:.1f} s"}
 
 
+def impact_2d(steps: int = 2000, warmup: int = 100):
+    """The 2-D impact configuration (D2Q9 FP32 1024 x 512, ratio 1000) from
+    its initial state: time per step over 'steps' steps after 'warmup', the
+    library's automatic tiling."""
+    import torch
+
+    from paper_2201_12404_amd import elmrt as E
+    from paper_2201_12404_amd import workloads as W
+
+    w = W.IMPACT_2D
+    sim = E.Simulation(E.params_for(w))
+    sim.init_fields(*W.initial_fields(w))
+    sim.step(warmup)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    sim.step(steps)
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    sim.close()
+    return {"workload": w.name, "steps": steps, "mlups": round(w.N * steps / wall / 1e6, 1),
+            "us_per_step": round(wall / steps * 1e6, 2)}
+
+
 def batched_vs_plain(steps: int = 2000, trial_steps: int = 4):
     """64 uneven D2Q9 static drops (FP32), each for 'steps' steps: one after
     the other through the single-simulation path, then all together as one
@@ -401,6 +424,8 @@ def main():
     if args.copy_probe:
         copy_probe()
     if not args.no_batched:
+        print("[bench] 2-D impact 1024x512", file=sys.stderr, flush=True)
+        out["impact_2d"] = impact_2d()
         print("[bench] batched vs plain (64 static drops)", file=sys.stderr, flush=True)
         ranges.push("batched vs plain")
         out["batched"] = batched_vs_plain()
