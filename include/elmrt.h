@@ -316,10 +316,10 @@ void elmrt_destroy(elmrt_sim* s);
  * elmrt_server_run: a round takes the resident jobs first in the scheduling
  * order (elmrt_server_set_policy: arrival order -- the default -- least
  * remaining work -- cells x steps -- first, or that with the oldest job
- * always first) until
- * their cells reach a fill budget (elmrt_server_set_fill, default 2^21
- * cells, at least one job), and advances them as one batch per lattice and
- * precision (the elmrt_batch_* machinery, without graphs): the costliest
+ * always first): the first of them, and after it those that fit the rest of
+ * a fill budget (elmrt_server_set_fill, default 2^21 cells), and advances them as one batch per lattice and
+ * precision (the elmrt_batch_* machinery, without graphs; a lattice and
+ * precision with one job in the round steps it as elmrt_step): the costliest
  * batch by chunk_steps, a cheaper one by proportionally more steps (bytes
  * per step: D2Q9 132 B, D3Q27 356 B per cell), none beyond the fewest steps a
  * member still needs, so every job stops exactly at its step count.
@@ -347,7 +347,8 @@ typedef struct elmrt_server elmrt_server;
 elmrt_status elmrt_server_create(void* dev_pool, size_t pool_bytes, void* stream, int64_t chunk_steps,
                                  elmrt_server** out);
 
-/* Cells a round advances at most (beyond the first job); >= 1. */
+/* Fill budget: cells a round advances at most, its first job aside (which
+ * always runs); a later job joins the round only if it fits.  >= 1. */
 elmrt_status elmrt_server_set_fill(elmrt_server* s, int64_t cells);
 
 /* Scheduling order of resident jobs: 0 arrival (the default), 1 least

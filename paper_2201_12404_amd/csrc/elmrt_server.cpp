@@ -1,11 +1,12 @@
 // elmrt_server.cpp -- a request loop over the C ABI of elmrt.h: jobs (problem
 // statement, initial fields, step count) are queued, admitted in arrival
 // order while their workspace fits a caller-owned device pool, kept resident,
-// and advanced together in rounds: every round the resident jobs first in
-// policy order (arrival, or least remaining work), up to a budget of cells
-// that occupies the device, form one batch per lattice and
-// precision (elmrt_batch_*) that advances by the chunk or by the fewest steps
-// any member still needs, so that jobs finish exactly; a job whose
+// and advanced together in rounds: every round the first resident job in
+// policy order (arrival, or least remaining work) and the later ones that fit
+// a budget of cells that occupies the device form one batch per lattice and
+// precision (elmrt_batch_*; a single job steps alone) that advances by the
+// chunk or by the fewest steps any member still needs, so that jobs finish
+// exactly; a job whose
 // instability flag is seen set (polled after every round without waiting) is
 // evicted and read out early.  A scheduling pass never waits for the device:
 // it reads out the jobs whose last round has completed and uploads newly
@@ -301,10 +302,12 @@ double cell_cost(int D) { return D == 3 ? 356.0 / 132.0 : 1.0; }
 // jobs that fit the pool (upload and initialisation on the io stream), and,
 // while fewer than two rounds are in flight, enqueue the next round on the
 // compute stream.  A round advances resident jobs with steps left, in
-// policy order (arrival, or least remaining work -- cells x steps -- first),
-// until their cells reach the fill budget: enough work to occupy the device,
-// while the others wait their turn instead of slowing every running one down.
-// Each (lattice, precision) group of the round is one batch; the costliest
+// policy order (arrival, or least remaining work -- cells x steps -- first):
+// the first one, and after it those that fit the rest of the fill budget:
+// enough work to occupy the device, while the others wait their turn instead
+// of slowing every running one down.
+// Each (lattice, precision) group of the round is one batch (a group of one
+// job steps through the single-simulation path); the costliest
 // group advances by the chunk, a cheaper one by proportionally more steps (so
 // that a small job beside a large one is not held to the large one's pace),
 // and no group beyond the fewest steps any of its members still needs, so
@@ -349,10 +352,13 @@ elmrt_status round_once(elmrt_server* s, bool* progressed)
             order.insert(order.begin(), oldest);
         }
     }
+    // the first job in order always runs; the others join while they fit the
+    // rest of the fill budget, so that two jobs which each fill the device
+    // are not put into one launch (it runs slower than the two alone)
     std::vector<Job*> running;
     int64_t cells = 0;
     for (Job* j : order) {
-        if (!running.empty() && cells >= s->fill) break;
+        if (!running.empty() && cells + (int64_t)j->N > s->fill) continue;
         running.push_back(j);
         cells += (int64_t)j->N;
     }
@@ -368,13 +374,20 @@ elmrt_status round_once(elmrt_server* s, bool* progressed)
         for (double c : cost) top = std::max(top, c);
         for (int gi = 0; gi < 4; ++gi) {
             Group& g = s->groups[gi];
-            if ((st = sync_batch(s, g, members[gi])) != ELMRT_OK) return st;
+            // a group of one job advances through the single-simulation path
+            // (the kernels of a job run alone, with no job table to read)
+            const bool alone = members[gi].size() == 1;
+            if ((st = sync_batch(s, g, alone ? std::vector<Job*>{} : members[gi])) != ELMRT_OK) return st;
             if (members[gi].empty()) continue;
             const double ratio = std::floor(top / cost[gi]);
             int64_t n = s->chunk * (int64_t)std::min(ratio, 1e6);
             for (Job* j : members[gi]) n = std::min(n, j->steps - j->done);
-            if ((st = elmrt_batch_step(g.batch, n)) != ELMRT_OK) return st;
-            g.used_round = s->round;
+            if (alone) {
+                if ((st = elmrt_step(members[gi][0]->sim, n)) != ELMRT_OK) return st;
+            } else {
+                if ((st = elmrt_batch_step(g.batch, n)) != ELMRT_OK) return st;
+                g.used_round = s->round;
+            }
             for (Job* j : members[gi]) {
                 j->done += n;
                 j->last_round = s->round;
