@@ -128,6 +128,27 @@ def test_fill_budget_takes_turns(policy):
     srv.close()
 
 
+def test_round_takes_only_jobs_that_fit():
+    """A round takes its first job, then only the later jobs that fit the
+    rest of the fill budget: with a budget of two 64^2 grids, arrival order
+    64^2, 128^2, 64^2, the first round advances the two small jobs (as one
+    batch) and not the large one; every result is that of the job alone."""
+    ws = [W.impact_job(2, 64, 10, 0.03, 8, 0), W.impact_job(2, 128, 1000, 0.05, 8, 1),
+          W.impact_job(2, 64, 100, 0.04, 8, 2)]
+    srv = E.Server(pool_bytes=1 << 28, chunk_steps=4)
+    srv.set_fill(2 * 64 * 64)
+    ids = [srv.submit(E.params_for(w), *W.initial_fields(w), 8) for w in ws]
+    srv.run(1)          # the first pass admits all three and runs one round
+    assert [srv.job(j)[2] for j in ids] == [4, 0, 4]
+    while srv.run(1) != (0, 0):
+        pass
+    for jid, w in zip(ids, ws):
+        rho_s, u_s, _ = srv.result(jid)
+        rho_a, u_a, _ = alone(w, 8)
+        assert np.array_equal(rho_s, rho_a) and np.array_equal(u_s, u_a)
+    srv.close()
+
+
 def test_unstable_job_is_evicted():
     """A job that goes unstable (BGK at nu = 0.0005 on a density-ratio-1000
     drop) is evicted once its polled flag is seen: it stops short of its step
