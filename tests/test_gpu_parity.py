@@ -701,3 +701,32 @@ def test_target_width_derives_kappa():
     assert np.array_equal(out[0], out[1])
     assert abs(k / O.kappa_for_width(w.eos["eos_a"], w.eos["eos_b"], w.eos["eos_R"], w.eos["acentric"],
                                      w.T_over_Tc, 6.0) - 1) < 1e-7
+
+
+def test_zero_steps_change_nothing():
+    """Zero steps are a valid, empty request: a simulation, a batch and a
+    served job with no steps keep the initial state bitwise (the populations
+    of f^eq at the initial fluid velocity, whose moments the read-outs give)."""
+    from dataclasses import replace
+    w = replace(_small(2, (0, 1), 0), precision=0)
+    rho0, u0 = W.initial_fields(w)
+    sim = E.Simulation(E.params_for(w))
+    sim.init_fields(rho0, u0)
+    f_init = sim.read_populations()
+    m_init = sim.read_macros()
+    sim.step(0)
+    assert np.array_equal(sim.read_populations(), f_init)
+    b = E.Batch([sim])
+    b.step(0)
+    b.close()
+    assert np.array_equal(sim.read_populations(), f_init)
+    sim.close()
+    srv = E.Server(pool_bytes=1 << 26, chunk_steps=4)
+    jid = srv.submit(E.params_for(w), rho0, u0, 0)
+    while srv.run(1) != (0, 0):
+        pass
+    st, _, done = srv.job(jid)
+    assert st == E.Server.DONE and done == 0
+    rho_s, u_s, sums_s = srv.result(jid)
+    assert np.array_equal(rho_s, m_init[0]) and np.array_equal(u_s, m_init[1])
+    srv.close()
