@@ -730,3 +730,32 @@ def test_zero_steps_change_nothing():
     rho_s, u_s, sums_s = srv.result(jid)
     assert np.array_equal(rho_s, m_init[0]) and np.array_equal(u_s, m_init[1])
     srv.close()
+
+
+def test_init_rejects_invalid_fields():
+    """elmrt_init_fields rejects a density that is not finite or not
+    positive and a velocity that is not finite (ELMRT_E_INVALID), and the
+    handle stays usable: a valid initialisation afterwards gives the state of
+    a fresh handle bitwise."""
+    from dataclasses import replace
+    w = replace(_small(2, (0, 1), 0), precision=0)
+    rho0, u0 = W.initial_fields(w)
+    sim = E.Simulation(E.params_for(w))
+    for bad_rho, bad_u in ((float("nan"), None), (0.0, None), (-1.0, None), (None, float("inf"))):
+        r, u = rho0.copy(), u0.copy()
+        if bad_rho is not None:
+            r[17] = bad_rho
+        else:
+            u[1, 17] = bad_u
+        with pytest.raises(E.ElmrtError) as err:
+            sim.init_fields(r, u)
+        assert err.value.status == E.ELMRT_E_INVALID
+    sim.init_fields(rho0, u0)
+    sim.step(3)
+    f = sim.read_populations()
+    sim.close()
+    fresh = E.Simulation(E.params_for(w))
+    fresh.init_fields(rho0, u0)
+    fresh.step(3)
+    assert np.array_equal(fresh.read_populations(), f)
+    fresh.close()

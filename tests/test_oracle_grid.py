@@ -203,3 +203,20 @@ def test_fluid_velocity_initialisation(D, n, bc):
     c = B.velocities(D).astype(float)
     for cell in (0, rho0.size // 2, rho0.size - 1):
         np.testing.assert_allclose(f[cell], O.equilibrium(D, rho[cell], u[:, cell]), atol=1e-15 * rl)
+
+
+@pytest.mark.parametrize("bad", [float("nan"), -0.1, 0.0])
+def test_step_counts_cells_without_a_valid_density(bad):
+    """The failure mode of the method is a density that stops being finite
+    and positive: a state holding one such cell is reported by the step's
+    statistics (the check the library's instability flag mirrors)."""
+    rho0, u0, rv, rl = _drop_state(2, (24, 20, 1))
+    p = O.Params(D=2, n=(24, 20, 1), bc=(0, 0, 0), kappa=0.03, nu_l=0.05, nu_v=0.05, rho_l=rl, rho_v=rv)
+    f = O.init_equilibrium(p, rho0, u0)
+    st = O.step(p, f, 1)
+    assert st.nonfinite == 0
+    rho1 = rho0.copy()
+    rho1[5 + 24 * 7] = bad
+    f = O.init_equilibrium(p, rho1, u0)
+    st = O.step(p, f, 1)
+    assert st.nonfinite >= 1
