@@ -776,3 +776,16 @@ def test_fp32_walls_and_odd_widths(D, bc, n):
     say(f"fp32 {D} {bc} {n}: " + fmt(n_))
     assert all(v < 1e-5 for v in n_.values()), n_
     assert abs(s_g[0] / s_o[0] - 1) < 1e-6
+
+
+@pytest.mark.parametrize("D,bc", [(2, (0, 0)), (3, (1, 0, 0)), (3, (0, 0, 1))])
+def test_fp32_bgk(D, bc):
+    """The FP32 kernels with the BGK collision (gamma = 2), 150 steps of the
+    small seeded cases at nu = 0.05: every norm within 1e-5 of the oracle."""
+    from dataclasses import replace
+    w = replace(_small(D, bc, 0), nu_liquid=0.05, nu_vapour=0.05)
+    rho_g, u_g, _, _ = run_gpu(w, 150, collision=1)
+    rho_o, u_o, _, _, _ = run_oracle(w, 150, collision=1)
+    n_ = fp32_norms(rho_g, u_g, rho_o, u_o)
+    say(f"fp32 bgk {D} {bc}: " + fmt(n_))
+    assert all(v < 1e-5 for v in n_.values()), n_
