@@ -359,34 +359,68 @@ def _ray_extent(line: np.ndarray, axis: int, step: int, mid: float) -> float:
     return n / 2.0
 
 
-def crown_radius(rho: np.ndarray, w: W.Workload, probe: float | None = None) -> float:
+def _ray_edges(line: np.ndarray, axis: int, step: int, mid: float) -> list:
+    """Distances from cell 'axis' along a line (as _ray_extent) to the outer
+    edge of every liquid run met within half the line, in order."""
+    n = len(line)
+    half = n // 2
+    edges, k = [], 0
+    while k <= half:
+        while k <= half and line[(axis + step * k) % n] <= mid:
+            k += 1
+        if k > half:
+            break
+        while k < half and line[(axis + step * (k + 1)) % n] > mid:
+            k += 1
+        if k >= half:
+            edges.append(n / 2.0)
+            break
+        a, b = line[(axis + step * k) % n], line[(axis + step * (k + 1)) % n]
+        edges.append(k + (a - mid) / (a - b))
+        k += 1
+    return edges
+
+
+def crown_radius(rho: np.ndarray, w: W.Workload, probe: float | None = None, near: float | None = None) -> float:
     """Spreading (crown base) radius of an impact, in the plane one interface
     width above the initial film surface (or 'probe' cells above it): the
     distance from the impact axis to the outer edge of the first liquid met
     going outward (density above the mean of the coexistence densities),
     averaged over the rays along +x and -x (2-D) or +-x and +-y (3-D; the
-    crown diameter is twice this).  Cells are x fastest; the last axis is
-    wall-normal."""
+    crown diameter is twice this).  With 'near' (cells) each ray takes the
+    liquid edge closest to it instead of the first one, which follows the
+    crown wall once an inner liquid ring forms inside it.  Cells are x
+    fastest; the last axis is wall-normal."""
     n = w.n
     mid = 0.5 * (w.rho_l + w.rho_v)
     z = int(round(w.film + (w.width if probe is None else probe)))
     f = np.asarray(rho).reshape(n[::-1])
     xc = int(round(w.centre[0]))
+
+    def ray(line, c, d):
+        if near is None:
+            return _ray_extent(line, c, d, mid)
+        edges = _ray_edges(line, c, d, mid)
+        return min(edges, key=lambda e: abs(e - near)) if edges else 0.0
+
     if w.D == 2:
-        return 0.5 * (_ray_extent(f[z], xc, 1, mid) + _ray_extent(f[z], xc, -1, mid))
+        return 0.5 * (ray(f[z], xc, 1) + ray(f[z], xc, -1))
     yc = int(round(w.centre[1]))
     plane = f[z]                                   # (ny, nx)
     rows = (plane[yc, :], plane[:, xc])
-    return 0.25 * sum(_ray_extent(line, c, d, mid) for line, c in zip(rows, (xc, yc)) for d in (1, -1))
+    return 0.25 * sum(ray(line, c, d) for line, c in zip(rows, (xc, yc)) for d in (1, -1))
 
 
 def crown_history(w: W.Workload, t_end: float = 1.0, samples: int = 20, collision: int = E.ELMRT_ENTROPIC,
-                  tiling=None, probes=(None,), progress=None) -> dict:
+                  tiling=None, probes=(None,), progress=None, track: bool = False) -> dict:
     """Run an impact and sample the crown radius (one series per probe
     height, crown_radius).  Time is counted from the geometric contact of the
     drop with the film (gap / U0 steps after the start) in units of
-    tau = 2 R0 / U0 (Sec. 3.2), up to t_end tau.  progress(step, t_tau,
-    radii) is called after every sample when given."""
+    tau = 2 R0 / U0 (Sec. 3.2), up to t_end tau.  With track, every sample
+    after the first takes on each ray the liquid edge closest to the previous
+    radius grown by the square-root law, sqrt(t / t_prev), so that the
+    series follows the crown wall when an inner liquid ring forms.
+    progress(step, t_tau, radii) is called after every sample when given."""
     gap = w.centre[-1] - w.radius - w.film
     tau = 2.0 * w.radius / w.u_impact
     t0 = gap / w.u_impact
@@ -402,7 +436,10 @@ def crown_history(w: W.Workload, t_end: float = 1.0, samples: int = 20, collisio
             done = m
             rho = sim.read_density()
             t.append((m - t0) / tau)
-            r.append([crown_radius(rho, w, p) / w.radius for p in probes])
+            near = [None] * len(probes)
+            if track and r and t[-2] > 0 and t[-1] > 0:
+                near = [r[-1][k] * w.radius * np.sqrt(t[-1] / t[-2]) for k in range(len(probes))]
+            r.append([crown_radius(rho, w, p, near=nr) / w.radius for p, nr in zip(probes, near)])
             if progress is not None:
                 progress(m, t[-1], r[-1])
     finally:
@@ -489,7 +526,8 @@ def paper_3d_impacts(R0: float = 80.0, cases=PAPER_3D_IMPACTS, a: float = IMPACT
     noise on the liquid velocity at the largest We.  sigma defaults to the
     Laplace-law surface tension at that a and kappa~.  Returns per case the
     crown diameter history d / (2 R0) against t / tau and its fits (power
-    law, square root with a free origin).  A case that goes unstable is
+    law, square root with a free origin), the crown followed from sample to
+    sample (crown_history with track).  A case that goes unstable is
     reported with stable = False."""
     tr = W.TR_OF_RATIO[1000]
     if sigma is None:
@@ -503,7 +541,7 @@ def paper_3d_impacts(R0: float = 80.0, cases=PAPER_3D_IMPACTS, a: float = IMPACT
         rec = dict(We=We, Re=Re, R0=R0, n=w.n, cells=w.N, u0=w.u_impact, nu_l=w.nu_liquid, sigma=sigma,
                    stable=True)
         try:
-            h = crown_history(w, t_end=t_end, samples=samples, progress=progress)
+            h = crown_history(w, t_end=t_end, samples=samples, progress=progress, track=True)
             rec.update(t_tau=h["t_tau"], d_2R0=h["r_R0"], steps=h["steps"])
             rec["n_fit"], rec["c"] = fit_sqrt(h["t_tau"], h["r_R0"], *window)
             rec["c_off"], rec["t_c"], rec["resid"] = fit_sqrt_offset(h["t_tau"], h["r_R0"], *window)

@@ -153,3 +153,23 @@ def test_liquid_noise_is_seeded_gaussian_in_the_liquid_only():
     assert abs(du[:, liquid].mean()) < 0.1 * s
     other = W.initial_fields(replace(w, seed=4))[1]
     assert not np.array_equal(other, u)
+
+
+def test_tracked_reading_follows_the_crown_wall_past_an_inner_ring():
+    """With an inner liquid ring inside the crown wall on the probe plane,
+    the first-edge reading gives the ring's outer edge; the tracked reading
+    (the edge closest to a given radius) gives the wall's, on every ray."""
+    w = S.impact_case(12.0, 0.05, 0.005, D=3, extent=(8, 8, 3))
+    nx, ny, nz = w.n
+    z = int(round(w.film + w.width))
+    X, Y = np.meshgrid(np.arange(nx) - w.centre[0], np.arange(ny) - w.centre[1])
+    R = np.hypot(X, Y)
+    rho = np.full((nz, ny, nx), w.rho_v)
+    rho[z] = np.where(((R >= 8) & (R <= 12)) | ((R >= 26) & (R <= 30)), w.rho_l, w.rho_v)
+    first = S.crown_radius(rho.ravel(), w)
+    tracked = S.crown_radius(rho.ravel(), w, near=28.0)
+    assert 12.0 <= first <= 13.5
+    assert 30.0 <= tracked <= 31.5
+    assert S.crown_radius(rho.ravel(), w, near=1.0) == first
+    assert S._ray_edges(rho[z][int(round(w.centre[1]))], int(round(w.centre[0])), 1, 0.5 * (w.rho_l + w.rho_v))[:2] \
+        == pytest.approx([first, tracked], abs=1.5)

@@ -175,7 +175,7 @@ def test_paper_3d_impact_reduced():
     the crown diameter grows, as t^n with 0.2 < n < 0.7 over 0.05 .. 0.3
     tau (measured 0.33: at this radius the film, 18 cells thick, merges with
     the drop early).  At the paper's R0 = 80 (6.0e8 cells) all three cases
-    run to 0.6 tau with n = 0.44-0.45 over 0.05 .. 0.5 tau (measured)."""
+    run to t = tau with n = 0.48-0.49 over 0.05 .. 1 tau (measured)."""
     (rec,) = S.paper_3d_impacts(R0=40.0, cases=S.PAPER_3D_IMPACTS[:1], t_end=0.3, samples=6, window=(0.05, 0.3))
     say(f"3-D We {rec['We']:g} Re {rec['Re']:g} R0 40: U0={rec['u0']:.4f} nu_l={rec['nu_l']:.5f} "
         f"sigma={rec['sigma']:.4f} stable={rec['stable']} d/2R0={np.round(rec.get('d_2R0', []), 3).tolist()} "
